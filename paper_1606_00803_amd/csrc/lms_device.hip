@@ -1,0 +1,776 @@
+// Device side of the smoothing library for gfx950 (MI355X): kernels and the
+// runtime around them (upload of the mesh arrays, scratch buffers, graph
+// capture of the sweep loop, device-side stopping rule).
+//
+// Compiled with -ffp-contract=off: the sweep sums and the quality arithmetic
+// are exactly the IEEE operations written (no fused multiply-add).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "lms_internal.hpp"
+
+namespace lms {
+
+#define HIP_CHECK(expr)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            fail(e_ == hipErrorOutOfMemory ? LMS_ERR_ALLOC : LMS_ERR_HIP,                  \
+                 std::string(#expr) + " failed: " + hipGetErrorString(e_));                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device-side state of Algorithm 1's stopping rule.
+struct StopState {
+    int32_t done;        // nonzero: stop; later sweeps in a captured chunk do nothing
+    int32_t iters;       // sweeps done so far
+    int32_t stopped_by;  // lms_stop_reason
+    int32_t pad;
+    double q0;
+    double q_prev;       // Q_{k-1}
+    double q_last;       // Q_k of the last evaluation
+    double last_dq;
+};
+
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
+
+// Workgroups are dealt to the XCDs round-robin.  Remap the launch index so
+// that each XCD walks one contiguous range of tiles: neighbouring tiles share
+// halo cache lines, and this keeps the sharing inside one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb / kXcds, r = nb % kXcds;
+    const int xcd = b % kXcds, local = b / kXcds;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi sweep, Eq. 1 for every free vertex: dst[v] = (sum of src[u] over the
+// neighbours u of v, in ascending label) / deg(v).  Fixed rows are empty and
+// are not written.
+//
+// One workgroup of BS threads owns BS consecutive rows.  Its slice of
+// row_ptr goes to LDS; then the whole workgroup streams the slice's
+// neighbour indices with coalesced loads and gathers the neighbour
+// coordinates into LDS (edge-parallel: all gathers independent, CAP entries
+// per pass); finally each thread sums its own row out of LDS in order and
+// divides.  A slice with more than CAP entries takes several passes; the
+// partial sums carry over, so the summation order stays the row's order.
+template <typename T, int BS, int CAP, bool SWZ>
+__global__ __launch_bounds__(BS) void k_jacobi(const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ col,
+                                               const T *__restrict__ sx, const T *__restrict__ sy,
+                                               T *__restrict__ dx, T *__restrict__ dy, int32_t n,
+                                               const StopState *__restrict__ st) {
+    static_assert(CAP % BS == 0, "CAP must be a multiple of BS");
+    constexpr int PER = CAP / BS;
+    __shared__ int32_t s_rp[BS + 1];
+    __shared__ T s_x[CAP];
+    __shared__ T s_y[CAP];
+    if (st && st->done) return;
+
+    const int nb = int(gridDim.x);
+    const int tile = SWZ ? xcd_tile(int(blockIdx.x), nb) : int(blockIdx.x);
+    const int32_t r0 = tile * BS;
+    const int tid = int(threadIdx.x);
+    const int rows = min(BS, n - r0);
+    for (int i = tid; i <= rows; i += BS) s_rp[i] = row_ptr[r0 + i];
+    __syncthreads();
+    const int32_t nz0 = s_rp[0], nz1 = s_rp[rows];
+    const int32_t my_b = tid < rows ? s_rp[tid] : 0;
+    const int32_t my_e = tid < rows ? s_rp[tid + 1] : 0;
+    T ax = T(0), ay = T(0);
+    for (int32_t base = nz0; base < nz1; base += CAP) {
+        const int cnt = min(CAP, nz1 - base);
+        int32_t u[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int j = tid + i * BS;
+            u[i] = j < cnt ? __builtin_nontemporal_load(col + base + j) : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int j = tid + i * BS;
+            if (j < cnt) {
+                s_x[j] = sx[u[i]];
+                s_y[j] = sy[u[i]];
+            }
+        }
+        __syncthreads();
+        const int32_t lo = max(my_b, base), hi = min(my_e, base + cnt);
+        for (int32_t j = lo; j < hi; ++j) {
+            ax += s_x[j - base];
+            ay += s_y[j - base];
+        }
+        __syncthreads();
+    }
+    if (my_e > my_b) {
+        const T c = T(my_e - my_b);
+        dx[r0 + tid] = ax / c;
+        dy[r0 + tid] = ay / c;
+    }
+}
+
+// Multicolour sweep of one colour, in place: every vertex of the colour reads
+// the current coordinates of its neighbours (none of which has this colour).
+template <typename T>
+__global__ __launch_bounds__(256) void k_colour(const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ col,
+                                                const int32_t *__restrict__ list, int32_t cnt, T *x,
+                                                T *y, const StopState *__restrict__ st) {
+    if (st && st->done) return;
+    const int32_t i = int32_t(blockIdx.x) * 256 + int32_t(threadIdx.x);
+    if (i >= cnt) return;
+    const int32_t v = list[i];
+    const int32_t b = row_ptr[v], e = row_ptr[v + 1];
+    T ax = T(0), ay = T(0);
+    for (int32_t j = b; j < e; ++j) {
+        const int32_t u = col[j];
+        ax += x[u];
+        ay += y[u];
+    }
+    const T c = T(e - b);
+    x[v] = ax / c;
+    y[v] = ay / c;
+}
+
+// ---------------------------------------------------------------------------
+// Quality (Section 3.2) of one triangle: shortest / longest Euclidean edge.
+template <typename T>
+__device__ __forceinline__ double tri_quality(const T *__restrict__ x, const T *__restrict__ y,
+                                              int32_t a, int32_t b, int32_t c) {
+    const double xa = double(x[a]), ya = double(y[a]);
+    const double xb = double(x[b]), yb = double(y[b]);
+    const double xc = double(x[c]), yc = double(y[c]);
+    double dx, dy;
+    dx = xb - xa;
+    dy = yb - ya;
+    const double e0 = dx * dx + dy * dy;
+    dx = xc - xb;
+    dy = yc - yb;
+    const double e1 = dx * dx + dy * dy;
+    dx = xa - xc;
+    dy = ya - yc;
+    const double e2 = dx * dx + dy * dy;
+    const double mn = fmin(fmin(e0, e1), e2);
+    const double mx = fmax(fmax(e0, e1), e2);
+    return mx > 0.0 ? sqrt(mn) / sqrt(mx) : 0.0;
+}
+
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double *s_red) {
+    // fixed-shape reduction: 64-lane wavefront butterfly, then the wave sums
+    // in wave order -- the same result for the same inputs on every run
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    if (lane == 0) s_red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BS / 64; ++w) t += s_red[w];
+    return t;  // valid in thread 0
+}
+
+// Per-block partial sums of q_t * w_t over a grid-stride range of triangles,
+// where w_t = sum over the corners of 1/|T(v)| (the 1/|V| of the global mean
+// is applied by the final reduction).  Optionally stores q_t.
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_quality(const int32_t *__restrict__ ta,
+                                                const int32_t *__restrict__ tb,
+                                                const int32_t *__restrict__ tc,
+                                                const double *__restrict__ tw,
+                                                const T *__restrict__ x, const T *__restrict__ y,
+                                                int64_t ntri, double *__restrict__ partials,
+                                                double *__restrict__ qt_out,
+                                                const StopState *__restrict__ st) {
+    __shared__ double s_red[BS / 64];
+    if (st && st->done) return;
+    double acc = 0.0;
+    const int64_t stride = int64_t(gridDim.x) * BS;
+    for (int64_t t = int64_t(blockIdx.x) * BS + threadIdx.x; t < ntri; t += stride) {
+        const double q = tri_quality(x, y, ta[t], tb[t], tc[t]);
+        if (qt_out) qt_out[t] = q;
+        acc += q * tw[t];
+    }
+    const double s = block_sum<BS>(acc, s_red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Sum of the partials in a fixed order, times 1/|V|.
+__device__ double reduce_partials(const double *__restrict__ partials, int nparts, double inv_n,
+                                  double *s_red) {
+    double acc = 0.0;
+    for (int i = int(threadIdx.x); i < nparts; i += 256) acc += partials[i];
+    const double s = block_sum<256>(acc, s_red);
+    return s * inv_n;
+}
+
+// Stopping rule of Algorithm 1, evaluated on the device after each sweep
+// (init: before the first sweep).  Single workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_stop(const double *__restrict__ partials, int nparts,
+                                              double inv_n, StopState *st, int init, int use_q_prev,
+                                              double q_prev_given, double tol, double goal,
+                                              int32_t max_iters) {
+    __shared__ double s_red[4];
+    if (st->done) return;
+    const double Q = reduce_partials(partials, nparts, inv_n, s_red);
+    if (threadIdx.x != 0) return;
+    if (init) {
+        const double q0 = use_q_prev ? q_prev_given : Q;
+        st->q0 = q0;
+        st->q_prev = q0;
+        st->q_last = q0;
+        st->iters = 0;
+        st->last_dq = __builtin_nan("");
+        if (q0 >= goal) {
+            st->stopped_by = LMS_STOP_GOAL;
+            st->done = 1;
+        } else if (max_iters <= 0) {
+            st->stopped_by = LMS_STOP_MAX_ITERS;
+            st->done = 1;
+        }
+        return;
+    }
+    const int32_t k = st->iters + 1;
+    const double dq = Q - st->q_prev;
+    st->iters = k;
+    st->q_last = Q;
+    st->last_dq = dq;
+    if (Q >= goal) {
+        st->stopped_by = LMS_STOP_GOAL;
+        st->done = 1;
+    } else if (dq < tol) {
+        st->stopped_by = LMS_STOP_TOL;
+        st->done = 1;
+    } else if (k >= max_iters) {
+        st->stopped_by = LMS_STOP_MAX_ITERS;
+        st->done = 1;
+    }
+    st->q_prev = Q;
+}
+
+__global__ void k_stop_reset(StopState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->done = 0;
+        st->iters = 0;
+        st->stopped_by = LMS_STOP_MAX_ITERS;
+        st->pad = 0;
+        st->q0 = st->q_prev = st->q_last = st->last_dq = __builtin_nan("");
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_out(const double *__restrict__ partials, int nparts,
+                                                    double inv_n, double *out) {
+    __shared__ double s_red[4];
+    const double Q = reduce_partials(partials, nparts, inv_n, s_red);
+    if (threadIdx.x == 0) *out = Q;
+}
+
+// Per-mesh quality of a batched handle: one workgroup per mesh, over the
+// mesh's contiguous range of triangles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_quality_mesh(const int32_t *__restrict__ ta,
+                                                      const int32_t *__restrict__ tb,
+                                                      const int32_t *__restrict__ tc,
+                                                      const double *__restrict__ tw,
+                                                      const T *__restrict__ x, const T *__restrict__ y,
+                                                      const int64_t *__restrict__ t_off,
+                                                      const int64_t *__restrict__ v_off,
+                                                      double *__restrict__ out) {
+    __shared__ double s_red[4];
+    const int mesh = int(blockIdx.x);
+    double acc = 0.0;
+    for (int64_t t = t_off[mesh] + threadIdx.x; t < t_off[mesh + 1]; t += 256)
+        acc += tri_quality(x, y, ta[t], tb[t], tc[t]) * tw[t];
+    const double s = block_sum<256>(acc, s_red);
+    if (threadIdx.x == 0) out[mesh] = s / double(v_off[mesh + 1] - v_off[mesh]);
+}
+
+// q_v = mean of q_t over the triangles containing v.
+__global__ __launch_bounds__(256) void k_vertex_quality(const int32_t *__restrict__ vt_ptr,
+                                                        const int32_t *__restrict__ vt,
+                                                        const double *__restrict__ qt, int32_t n,
+                                                        double *__restrict__ qv) {
+    const int32_t v = int32_t(blockIdx.x) * 256 + int32_t(threadIdx.x);
+    if (v >= n) return;
+    double s = 0.0;
+    const int32_t b = vt_ptr[v], e = vt_ptr[v + 1];
+    for (int32_t i = b; i < e; ++i) s += qt[vt[i]];
+    qv[v] = s / double(e - b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_permute(const int32_t *__restrict__ new2old,
+                                                 const T *__restrict__ sx, const T *__restrict__ sy,
+                                                 T *__restrict__ dx, T *__restrict__ dy, int32_t n,
+                                                 int inverse) {
+    const int32_t k = int32_t(blockIdx.x) * 256 + int32_t(threadIdx.x);
+    if (k >= n) return;
+    const int32_t v = new2old[k];
+    if (inverse) {
+        dx[v] = sx[k];
+        dy[v] = sy[k];
+    } else {
+        dx[k] = sx[v];
+        dy[k] = sy[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Runtime
+
+namespace {
+
+constexpr int kSweepBS = 256;
+constexpr int kSweepCap = 2048;
+constexpr int kQualBS = 256;
+constexpr int kQualMaxBlocks = 1024;
+constexpr int kChunk = 16;  // sweeps per captured chunk under the stopping rule (even)
+
+struct GraphEntry {
+    std::string key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+bool env_flag(const char *name, bool dflt) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return !(v[0] == '0' || v[0] == 'n' || v[0] == 'N' || v[0] == 'f' || v[0] == 'F');
+}
+
+}  // namespace
+
+struct DeviceState {
+    int device = -1;
+    uint64_t version = ~uint64_t(0);
+    std::vector<void *> arrays;  // mesh arrays of the current version
+    int32_t *row_ptr = nullptr, *col = nullptr, *color_list = nullptr, *new2old = nullptr;
+    int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
+    double *tw = nullptr;
+    int64_t *t_off = nullptr, *v_off = nullptr;
+    // scratch, kept across versions
+    double *partials = nullptr;
+    int nparts = 0;
+    double *qt = nullptr;
+    size_t qt_cap = 0;
+    double *qout = nullptr;
+    double *qmesh = nullptr;
+    StopState *st = nullptr;
+    StopState *h_st = nullptr;  // pinned host mirror
+    void *tmp[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [precision][x|y]
+    size_t tmp_n[2] = {0, 0};
+    hipStream_t cap = nullptr;
+    std::vector<GraphEntry> graphs;
+    bool use_graphs = true;
+};
+
+namespace {
+
+void free_graphs(DeviceState *d) {
+    for (auto &g : d->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    d->graphs.clear();
+}
+
+void free_arrays(DeviceState *d) {
+    for (void *p : d->arrays) (void)hipFree(p);
+    d->arrays.clear();
+}
+
+template <class T>
+T *upload(DeviceState *d, const std::vector<T> &v) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    HIP_CHECK(hipMalloc(&p, bytes));
+    d->arrays.push_back(p);
+    if (!v.empty()) HIP_CHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return static_cast<T *>(p);
+}
+
+int quality_blocks(int64_t ntri) {
+    const int64_t need = (ntri + kQualBS - 1) / kQualBS;
+    return int(std::max<int64_t>(1, std::min<int64_t>(need, kQualMaxBlocks)));
+}
+
+// Make the device copy of the mesh current (first device call, or after a
+// reorder) on the current device.
+DeviceState &ensure_device(Mesh &M) {
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (!M.dev) {
+        M.dev.reset(new DeviceState());
+        DeviceState *d = M.dev.get();
+        d->device = dev;
+        d->use_graphs = env_flag("LMS_GRAPH", true);
+        HIP_CHECK(hipStreamCreateWithFlags(&d->cap, hipStreamNonBlocking));
+        HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d->partials), sizeof(double) * kQualMaxBlocks));
+        d->nparts = kQualMaxBlocks;
+        HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d->qout), sizeof(double)));
+        HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d->st), sizeof(StopState)));
+        HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&d->h_st), sizeof(StopState), hipHostMallocDefault));
+    }
+    DeviceState *d = M.dev.get();
+    if (d->device != dev)
+        fail(LMS_ERR_STATE, "handle lives on device " + std::to_string(d->device) + " but device " +
+                                std::to_string(dev) + " is current");
+    if (d->version != M.version) {
+        free_graphs(d);
+        free_arrays(d);
+        d->version = ~uint64_t(0);
+        d->row_ptr = upload(d, M.row_ptr);
+        d->col = upload(d, M.col);
+        d->color_list = upload(d, M.color_list);
+        d->new2old = upload(d, M.new2old);
+        d->ta = upload(d, M.ta);
+        d->tb = upload(d, M.tb);
+        d->tc = upload(d, M.tc);
+        d->tw = upload(d, M.tw);
+        d->vt_ptr = upload(d, M.vt_ptr);
+        d->vt = upload(d, M.vt);
+        d->t_off = upload(d, M.t_off);
+        d->v_off = upload(d, M.v_off);
+        void *qm = nullptr;
+        HIP_CHECK(hipMalloc(&qm, sizeof(double) * size_t(M.n_mesh)));
+        d->arrays.push_back(qm);
+        d->qmesh = static_cast<double *>(qm);
+        d->version = M.version;
+    }
+    return *d;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+size_t elem_size(lms_precision p) { return p == LMS_FP64 ? sizeof(double) : sizeof(float); }
+
+void check_precision(lms_precision p) {
+    if (p != LMS_FP64 && p != LMS_FP32) fail(LMS_ERR_ARG, "unknown precision");
+}
+
+void launch_check() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(LMS_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+}
+
+template <typename T>
+void launch_sweep(const DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
+                  const StopState *st, hipStream_t s) {
+    const int nb = (M.n + kSweepBS - 1) / kSweepBS;
+    k_jacobi<T, kSweepBS, kSweepCap, true><<<nb, kSweepBS, 0, s>>>(d.row_ptr, d.col, sx, sy, dx, dy, M.n, st);
+}
+
+template <typename T>
+void launch_colour_sweep(const DeviceState &d, const Mesh &M, T *x, T *y, const StopState *st,
+                         hipStream_t s) {
+    for (int32_t c = 0; c < M.n_colors; ++c) {
+        const int32_t b = M.color_ptr[c], cnt = M.color_ptr[c + 1] - b;
+        if (cnt == 0) continue;
+        k_colour<T><<<(cnt + 255) / 256, 256, 0, s>>>(d.row_ptr, d.col, d.color_list + b, cnt, x, y, st);
+    }
+}
+
+template <typename T>
+void launch_quality(const DeviceState &d, const Mesh &M, const T *x, const T *y, double *qt_out,
+                    const StopState *st, hipStream_t s) {
+    k_quality<T, kQualBS><<<quality_blocks(M.T), kQualBS, 0, s>>>(d.ta, d.tb, d.tc, d.tw, x, y, M.T,
+                                                                   d.partials, qt_out, st);
+}
+
+void launch_stop(const DeviceState &d, const Mesh &M, int init, const lms_smooth_opts &o, hipStream_t s) {
+    const bool use_prev = !std::isnan(o.q_prev);
+    k_stop<<<1, 256, 0, s>>>(d.partials, quality_blocks(M.T), 1.0 / double(M.n), d.st, init, use_prev ? 1 : 0,
+                             use_prev ? o.q_prev : 0.0, o.tol, o.goal, o.max_iters);
+}
+
+// Run `body(stream)` either directly on `s`, or captured once into a graph
+// (cached under `key`) that is then launched on `s`.
+template <class F>
+void run_maybe_graph(DeviceState &d, const std::string &key, hipStream_t s, F body) {
+    if (!d.use_graphs) {
+        body(s);
+        launch_check();
+        return;
+    }
+    for (auto &g : d.graphs)
+        if (g.key == key) {
+            HIP_CHECK(hipGraphLaunch(g.exec, s));
+            return;
+        }
+    GraphEntry g;
+    g.key = key;
+    HIP_CHECK(hipStreamBeginCapture(d.cap, hipStreamCaptureModeRelaxed));
+    body(d.cap);
+    hipError_t le = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(d.cap, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        fail(LMS_ERR_HIP, std::string("kernel launch failed during capture: ") + hipGetErrorString(le));
+    }
+    if (ce != hipSuccess) fail(LMS_ERR_HIP, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(ce));
+    g.graph = graph;
+    hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        fail(LMS_ERR_HIP, std::string("hipGraphInstantiate failed: ") + hipGetErrorString(ie));
+    }
+    if (d.graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(d.graphs.front().exec);
+        (void)hipGraphDestroy(d.graphs.front().graph);
+        d.graphs.erase(d.graphs.begin());
+    }
+    d.graphs.push_back(g);
+    HIP_CHECK(hipGraphLaunch(g.exec, s));
+}
+
+std::string ptr_key(const void *p) { return std::to_string(reinterpret_cast<uintptr_t>(p)); }
+
+std::string dbl_key(double v) {
+    uint64_t bits = 0;
+    std::memcpy(&bits, &v, sizeof(bits));
+    return std::to_string(bits);
+}
+
+void *ensure_tmp(DeviceState &d, lms_precision p, int which, int32_t n) {
+    const int pi = p == LMS_FP64 ? 0 : 1;
+    if (d.tmp_n[pi] < size_t(n)) {
+        for (int w = 0; w < 2; ++w) {
+            if (d.tmp[pi][w]) (void)hipFree(d.tmp[pi][w]);
+            d.tmp[pi][w] = nullptr;
+        }
+        d.tmp_n[pi] = 0;
+        for (int w = 0; w < 2; ++w) HIP_CHECK(hipMalloc(&d.tmp[pi][w], elem_size(p) * size_t(n)));
+        d.tmp_n[pi] = size_t(n);
+        free_graphs(&d);  // graphs may have captured the old pointers
+    }
+    return d.tmp[pi][which];
+}
+
+bool overlaps(const void *a, const void *b, size_t bytes) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+template <typename T>
+void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precision p, lms_scheme sch,
+                  const lms_smooth_opts &o, hipStream_t s, lms_smooth_result &r) {
+    const std::string base = std::string(p == LMS_FP64 ? "f64" : "f32") + "|" + ptr_key(x) + "|" +
+                             ptr_key(y) + "|" + ptr_key(tx) + "|" + ptr_key(ty);
+    const size_t bytes = sizeof(T) * size_t(M.n);
+    const bool jacobi = sch == LMS_JACOBI;
+    if (jacobi) {
+        // both buffers start as P_0: fixed vertices are then right in either
+        HIP_CHECK(hipMemcpyAsync(tx, x, bytes, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(ty, y, bytes, hipMemcpyDeviceToDevice, s));
+    }
+    if (!o.check_quality) {
+        const int32_t K = o.max_iters;
+        if (K > 0) {
+            run_maybe_graph(d, "fixed|" + base + "|" + std::to_string(int(sch)) + "|" + std::to_string(K), s,
+                            [&](hipStream_t cs) {
+                                for (int32_t k = 0; k < K; ++k) {
+                                    if (!jacobi) {
+                                        launch_colour_sweep<T>(d, M, x, y, nullptr, cs);
+                                    } else if (k % 2 == 0) {
+                                        launch_sweep<T>(d, M, x, y, tx, ty, nullptr, cs);
+                                    } else {
+                                        launch_sweep<T>(d, M, tx, ty, x, y, nullptr, cs);
+                                    }
+                                }
+                            });
+        }
+        if (jacobi && (K % 2 == 1)) {
+            HIP_CHECK(hipMemcpyAsync(x, tx, bytes, hipMemcpyDeviceToDevice, s));
+            HIP_CHECK(hipMemcpyAsync(y, ty, bytes, hipMemcpyDeviceToDevice, s));
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        r.iters = K;
+        r.stopped_by = LMS_STOP_MAX_ITERS;
+        r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
+        return;
+    }
+    // Stopping rule on the device: Q_0, then chunks of sweeps each followed by
+    // a quality evaluation and the stop test; sweeps after the stop do nothing.
+    k_stop_reset<<<1, 64, 0, s>>>(d.st);
+    launch_quality<T>(d, M, x, y, nullptr, nullptr, s);
+    launch_stop(d, M, 1, o, s);
+    launch_check();
+    const std::string key = "stop|" + base + "|" + std::to_string(int(sch)) + "|" + dbl_key(o.tol) + "|" + dbl_key(o.goal) +
+                            "|" + std::to_string(o.max_iters);
+    for (;;) {
+        HIP_CHECK(hipMemcpyAsync(d.h_st, d.st, sizeof(StopState), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (d.h_st->done) break;
+        run_maybe_graph(d, key, s, [&](hipStream_t cs) {
+            for (int k = 0; k < kChunk; ++k) {
+                const bool fwd = (k % 2 == 0);
+                if (!jacobi) {
+                    launch_colour_sweep<T>(d, M, x, y, d.st, cs);
+                    launch_quality<T>(d, M, x, y, nullptr, d.st, cs);
+                } else if (fwd) {
+                    launch_sweep<T>(d, M, x, y, tx, ty, d.st, cs);
+                    launch_quality<T>(d, M, tx, ty, nullptr, d.st, cs);
+                } else {
+                    launch_sweep<T>(d, M, tx, ty, x, y, d.st, cs);
+                    launch_quality<T>(d, M, x, y, nullptr, d.st, cs);
+                }
+                launch_stop(d, M, 0, o, cs);
+            }
+        });
+    }
+    const StopState h = *d.h_st;
+    if (jacobi && (h.iters % 2 == 1)) {
+        HIP_CHECK(hipMemcpyAsync(x, tx, bytes, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(y, ty, bytes, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    r.iters = h.iters;
+    r.stopped_by = h.stopped_by;
+    r.q0 = h.q0;
+    r.q_final = h.q_last;
+    r.last_dq = h.last_dq;
+}
+
+}  // namespace
+
+void destroy_device_state(DeviceState *d) {
+    if (!d) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (d->device >= 0) (void)hipSetDevice(d->device);
+    free_graphs(d);
+    free_arrays(d);
+    for (auto &pt : d->tmp)
+        for (void *p : pt)
+            if (p) (void)hipFree(p);
+    if (d->partials) (void)hipFree(d->partials);
+    if (d->qt) (void)hipFree(d->qt);
+    if (d->qout) (void)hipFree(d->qout);
+    if (d->st) (void)hipFree(d->st);
+    if (d->h_st) (void)hipHostFree(d->h_st);
+    if (d->cap) (void)hipStreamDestroy(d->cap);
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete d;
+}
+
+void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lms_precision p, int inverse,
+                 void *stream) {
+    check_precision(p);
+    if (!sx || !sy || !dx || !dy) fail(LMS_ERR_ARG, "null coordinate pointer");
+    const size_t bytes = elem_size(p) * size_t(M.n);
+    if (overlaps(sx, dx, bytes) || overlaps(sx, dy, bytes) || overlaps(sy, dx, bytes) || overlaps(sy, dy, bytes))
+        fail(LMS_ERR_ARG, "lms_permute source and destination overlap");
+    DeviceState &d = ensure_device(M);
+    hipStream_t s = as_stream(stream);
+    const int nb = (M.n + 255) / 256;
+    if (p == LMS_FP64)
+        k_permute<double><<<nb, 256, 0, s>>>(d.new2old, static_cast<const double *>(sx), static_cast<const double *>(sy),
+                                             static_cast<double *>(dx), static_cast<double *>(dy), M.n, inverse);
+    else
+        k_permute<float><<<nb, 256, 0, s>>>(d.new2old, static_cast<const float *>(sx), static_cast<const float *>(sy),
+                                            static_cast<float *>(dx), static_cast<float *>(dy), M.n, inverse);
+    launch_check();
+}
+
+void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lms_precision p, void *stream) {
+    check_precision(p);
+    if (!sx || !sy || !dx || !dy) fail(LMS_ERR_ARG, "null coordinate pointer");
+    const size_t bytes = elem_size(p) * size_t(M.n);
+    if (overlaps(sx, dx, bytes) || overlaps(sx, dy, bytes) || overlaps(sy, dx, bytes) || overlaps(sy, dy, bytes))
+        fail(LMS_ERR_ARG, "a Jacobi sweep cannot run in place");
+    DeviceState &d = ensure_device(M);
+    hipStream_t s = as_stream(stream);
+    if (p == LMS_FP64)
+        launch_sweep<double>(d, M, static_cast<const double *>(sx), static_cast<const double *>(sy),
+                             static_cast<double *>(dx), static_cast<double *>(dy), nullptr, s);
+    else
+        launch_sweep<float>(d, M, static_cast<const float *>(sx), static_cast<const float *>(sy),
+                            static_cast<float *>(dx), static_cast<float *>(dy), nullptr, s);
+    launch_check();
+}
+
+void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p, lms_scheme sch,
+                const lms_smooth_opts &o, void *stream, lms_smooth_result &r) {
+    check_precision(p);
+    if (sch != LMS_JACOBI && sch != LMS_MULTICOLOR) fail(LMS_ERR_ARG, "unknown scheme");
+    if (!x || !y) fail(LMS_ERR_ARG, "null coordinate pointer");
+    if (o.max_iters < 0) fail(LMS_ERR_ARG, "max_iters must be >= 0");
+    if (std::isnan(o.tol) || std::isnan(o.goal)) fail(LMS_ERR_ARG, "tol and goal must not be NaN");
+    const size_t bytes = elem_size(p) * size_t(M.n);
+    if (overlaps(x, y, bytes)) fail(LMS_ERR_ARG, "x and y overlap");
+    DeviceState &d = ensure_device(M);
+    if (sch == LMS_JACOBI) {
+        if ((tx == nullptr) != (ty == nullptr)) fail(LMS_ERR_ARG, "give both tx and ty, or neither");
+        if (!tx) {
+            tx = ensure_tmp(d, p, 0, M.n);
+            ty = ensure_tmp(d, p, 1, M.n);
+        }
+        if (overlaps(tx, ty, bytes) || overlaps(tx, x, bytes) || overlaps(tx, y, bytes) || overlaps(ty, x, bytes) ||
+            overlaps(ty, y, bytes))
+            fail(LMS_ERR_ARG, "Jacobi scratch buffers must not overlap the coordinates");
+    }
+    hipStream_t s = as_stream(stream);
+    if (p == LMS_FP64)
+        smooth_typed<double>(M, d, static_cast<double *>(x), static_cast<double *>(y), static_cast<double *>(tx),
+                             static_cast<double *>(ty), p, sch, o, s, r);
+    else
+        smooth_typed<float>(M, d, static_cast<float *>(x), static_cast<float *>(y), static_cast<float *>(tx),
+                            static_cast<float *>(ty), p, sch, o, s, r);
+}
+
+void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global, double *q_vertex,
+                 double *q_mesh, void *stream) {
+    check_precision(p);
+    if (!x || !y) fail(LMS_ERR_ARG, "null coordinate pointer");
+    DeviceState &d = ensure_device(M);
+    hipStream_t s = as_stream(stream);
+    if (q_mesh) {
+        if (p == LMS_FP64)
+            k_quality_mesh<double><<<M.n_mesh, 256, 0, s>>>(d.ta, d.tb, d.tc, d.tw, static_cast<const double *>(x),
+                                                            static_cast<const double *>(y), d.t_off, d.v_off, d.qmesh);
+        else
+            k_quality_mesh<float><<<M.n_mesh, 256, 0, s>>>(d.ta, d.tb, d.tc, d.tw, static_cast<const float *>(x),
+                                                           static_cast<const float *>(y), d.t_off, d.v_off, d.qmesh);
+        launch_check();
+        HIP_CHECK(hipMemcpyAsync(q_mesh, d.qmesh, sizeof(double) * size_t(M.n_mesh), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        return;
+    }
+    double *qt_out = nullptr;
+    if (q_vertex) {
+        if (d.qt_cap < size_t(M.T)) {
+            if (d.qt) (void)hipFree(d.qt);
+            d.qt = nullptr;
+            d.qt_cap = 0;
+            HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d.qt), sizeof(double) * size_t(M.T)));
+            d.qt_cap = size_t(M.T);
+        }
+        qt_out = d.qt;
+    }
+    if (p == LMS_FP64)
+        launch_quality<double>(d, M, static_cast<const double *>(x), static_cast<const double *>(y), qt_out, nullptr, s);
+    else
+        launch_quality<float>(d, M, static_cast<const float *>(x), static_cast<const float *>(y), qt_out, nullptr, s);
+    launch_check();
+    if (q_vertex) {
+        k_vertex_quality<<<(M.n + 255) / 256, 256, 0, s>>>(d.vt_ptr, d.vt, d.qt, M.n, q_vertex);
+        launch_check();
+    }
+    if (q_global) {
+        k_reduce_out<<<1, 256, 0, s>>>(d.partials, quality_blocks(M.T), 1.0 / double(M.n), d.qout);
+        launch_check();
+        HIP_CHECK(hipMemcpyAsync(q_global, d.qout, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+}
+
+}  // namespace lms

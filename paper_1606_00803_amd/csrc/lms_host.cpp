@@ -1,0 +1,401 @@
+// Host side of the smoothing library: adjacency build, host quality,
+// orderings (ORI / BFS / RDR / random), multicolour schedule and relabelling.
+//
+// Compiled with -ffp-contract=off: the vertex qualities RDR sorts by are
+// computed with exactly the IEEE operations written here, so any other code
+// performing the same operations in the same order gets the same bits.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <numeric>
+
+#include "lms_internal.hpp"
+
+namespace lms {
+
+void fail(lms_status code, const std::string &msg) { throw Error{code, msg}; }
+
+namespace {
+
+template <class T>
+void resize_or_fail(std::vector<T> &v, size_t n) {
+    try {
+        v.assign(n, T());
+    } catch (const std::bad_alloc &) {
+        fail(LMS_ERR_ALLOC, "host allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+}
+
+}  // namespace
+
+// Neighbours of Eq. 1: for every vertex, the distinct vertices sharing a
+// triangle edge with it.  An edge seen in exactly one triangle is a boundary
+// edge and fixes both endpoints (unless the caller gave a mask).
+void build_mesh(Mesh &M, int32_t n, int64_t T, const int32_t *tri, const uint8_t *fixed,
+                int32_t n_mesh, const int64_t *v_off, const int64_t *t_off) {
+    if (n <= 0) fail(LMS_ERR_ARG, "n must be positive");
+    if (T <= 0) fail(LMS_ERR_ARG, "n_tri must be positive");
+    if (T > (int64_t(1) << 40)) fail(LMS_ERR_ARG, "n_tri too large (more than 2^40 triangles)");
+    if (!tri) fail(LMS_ERR_ARG, "tri is NULL");
+    M.n = n;
+    M.T = T;
+    M.n_mesh = n_mesh;
+    M.v_off.assign(v_off, v_off + n_mesh + 1);
+    M.t_off.assign(t_off, t_off + n_mesh + 1);
+
+    resize_or_fail(M.tri0, size_t(3 * T));
+    for (int32_t i = 0; i < n_mesh; ++i) {
+        const int64_t vb = v_off[i], ve = v_off[i + 1];
+        const int64_t nv = ve - vb;
+        for (int64_t t = t_off[i]; t < t_off[i + 1]; ++t) {
+            for (int c = 0; c < 3; ++c) {
+                const int64_t v = tri[3 * t + c];
+                if (v < 0 || v >= nv)
+                    fail(LMS_ERR_MESH, "triangle " + std::to_string(t) + " refers to vertex " +
+                                           std::to_string(v) + " outside [0, " + std::to_string(nv) + ")");
+                M.tri0[3 * t + c] = int32_t(v + vb);
+            }
+            const int32_t *p = &M.tri0[3 * t];
+            if (p[0] == p[1] || p[1] == p[2] || p[0] == p[2])
+                fail(LMS_ERR_MESH, "triangle " + std::to_string(t) + " repeats a vertex");
+        }
+    }
+
+    // triangles per vertex, and vertex -> triangle incidence (counting sort,
+    // ascending triangle index within each vertex)
+    resize_or_fail(M.tcount0, size_t(n));
+    for (int64_t i = 0; i < 3 * T; ++i) M.tcount0[M.tri0[i]]++;
+    for (int32_t v = 0; v < n; ++v)
+        if (M.tcount0[v] == 0) fail(LMS_ERR_MESH, "vertex " + std::to_string(v) + " is not referenced by any triangle");
+    resize_or_fail(M.vt_ptr0, size_t(n) + 1);
+    for (int32_t v = 0; v < n; ++v) M.vt_ptr0[v + 1] = M.vt_ptr0[v] + M.tcount0[v];
+    resize_or_fail(M.vt0, size_t(3 * T));
+    {
+        std::vector<int64_t> fill(M.vt_ptr0.begin(), M.vt_ptr0.end() - 1);
+        for (int64_t t = 0; t < T; ++t)
+            for (int c = 0; c < 3; ++c) M.vt0[fill[M.tri0[3 * t + c]]++] = int32_t(t);
+    }
+
+    // unique neighbours with edge multiplicities
+    resize_or_fail(M.adj_ptr0, size_t(n) + 1);
+    resize_or_fail(M.fixed0, size_t(n));
+    std::vector<int32_t> buf;
+    std::vector<int32_t> tmp;
+    try {
+        tmp.reserve(size_t(6 * T));
+    } catch (const std::bad_alloc &) {
+        fail(LMS_ERR_ALLOC, "host allocation for the adjacency failed");
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        buf.clear();
+        for (int64_t i = M.vt_ptr0[v]; i < M.vt_ptr0[v + 1]; ++i) {
+            const int32_t *p = &M.tri0[3 * int64_t(M.vt0[i])];
+            for (int c = 0; c < 3; ++c)
+                if (p[c] != v) buf.push_back(p[c]);
+        }
+        std::sort(buf.begin(), buf.end());
+        bool on_boundary = false;
+        for (size_t a = 0; a < buf.size();) {
+            size_t b = a;
+            while (b < buf.size() && buf[b] == buf[a]) ++b;
+            const size_t mult = b - a;
+            if (mult > 2)
+                fail(LMS_ERR_MESH, "edge (" + std::to_string(v) + ", " + std::to_string(buf[a]) +
+                                       ") is shared by more than two triangles");
+            if (mult == 1) on_boundary = true;
+            tmp.push_back(buf[a]);
+            a = b;
+        }
+        M.adj_ptr0[v + 1] = int64_t(tmp.size());
+        M.fixed0[v] = fixed ? uint8_t(fixed[v] != 0) : uint8_t(on_boundary);
+    }
+    M.adj0.swap(tmp);
+
+    M.n_free = 0;
+    M.max_degree = 0;
+    int64_t nnz = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (M.fixed0[v]) continue;
+        const int64_t d = M.adj_ptr0[v + 1] - M.adj_ptr0[v];
+        if (d == 0) fail(LMS_ERR_MESH, "free vertex " + std::to_string(v) + " has no neighbours");
+        M.n_free++;
+        M.max_degree = std::max<int32_t>(M.max_degree, int32_t(d));
+        nnz += d;
+    }
+    if (nnz >= (int64_t(1) << 31)) fail(LMS_ERR_ARG, "smoothing adjacency exceeds 2^31 entries");
+
+    // Multicolour schedule: greedy first-fit over the graph induced on free
+    // vertices, in ascending input label, smallest colour not taken by an
+    // already coloured free neighbour.
+    resize_or_fail(M.color0, size_t(n));
+    std::fill(M.color0.begin(), M.color0.end(), -1);
+    std::vector<int32_t> seen_at;  // seen_at[c] == v: colour c taken around v
+    M.n_colors = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (M.fixed0[v]) continue;
+        for (int64_t j = M.adj_ptr0[v]; j < M.adj_ptr0[v + 1]; ++j) {
+            const int32_t c = M.color0[M.adj0[j]];
+            if (c >= 0) {
+                if (size_t(c) >= seen_at.size()) seen_at.resize(size_t(c) + 1, -1);
+                seen_at[c] = v;
+            }
+        }
+        int32_t c = 0;
+        while (size_t(c) < seen_at.size() && seen_at[c] == v) ++c;
+        M.color0[v] = c;
+        M.n_colors = std::max(M.n_colors, c + 1);
+    }
+
+    std::vector<int32_t> ident(static_cast<size_t>(n));
+    std::iota(ident.begin(), ident.end(), 0);
+    relabel(M, LMS_ORI, std::move(ident));
+}
+
+// Section 3.2: triangle quality = shortest / longest Euclidean edge length
+// (0 when the longest edge has length 0); vertex quality = mean over its
+// triangles, summed in ascending triangle index.
+void vertex_quality_host(const Mesh &M, const double *x, const double *y, double *q) {
+    std::vector<double> qt(static_cast<size_t>(M.T));
+    for (int64_t t = 0; t < M.T; ++t) {
+        const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
+        double dx, dy;
+        dx = x[b] - x[a];
+        dy = y[b] - y[a];
+        const double e0 = dx * dx + dy * dy;
+        dx = x[c] - x[b];
+        dy = y[c] - y[b];
+        const double e1 = dx * dx + dy * dy;
+        dx = x[a] - x[c];
+        dy = y[a] - y[c];
+        const double e2 = dx * dx + dy * dy;
+        const double mn = std::min(std::min(e0, e1), e2);
+        const double mx = std::max(std::max(e0, e1), e2);
+        qt[t] = mx > 0.0 ? std::sqrt(mn) / std::sqrt(mx) : 0.0;
+    }
+    for (int32_t v = 0; v < M.n; ++v) {
+        double s = 0.0;
+        for (int64_t i = M.vt_ptr0[v]; i < M.vt_ptr0[v + 1]; ++i) s += qt[M.vt0[i]];
+        q[v] = s / double(M.tcount0[v]);
+    }
+}
+
+// Breadth-first search from label 0, neighbours in ascending label, restart
+// at the smallest unvisited label.  Meshes of a batch are separate
+// components in label order, so each one is ordered within its own range.
+std::vector<int32_t> order_bfs(const Mesh &M) {
+    std::vector<int32_t> out;
+    out.reserve(size_t(M.n));
+    std::vector<uint8_t> seen(size_t(M.n), 0);
+    std::vector<int32_t> queue(size_t(M.n));
+    for (int32_t s = 0; s < M.n; ++s) {
+        if (seen[s]) continue;
+        size_t head = 0, tail = 0;
+        queue[tail++] = s;
+        seen[s] = 1;
+        while (head < tail) {
+            const int32_t v = queue[head++];
+            out.push_back(v);
+            for (int64_t j = M.adj_ptr0[v]; j < M.adj_ptr0[v + 1]; ++j) {
+                const int32_t u = M.adj0[j];
+                if (!seen[u]) {
+                    seen[u] = 1;
+                    queue[tail++] = u;
+                }
+            }
+        }
+    }
+    return out;
+}
+
+// Algorithm 2 (RDR), per mesh.  Vertices are compared by (quality, label).
+// Starting from each not-yet-processed interior vertex in that order, the
+// vertex is placed if it is not yet; then repeatedly: the unprocessed
+// neighbours of the current vertex are taken in (quality, label) order, the
+// ones not yet placed are appended, and the walk moves to the first of them
+// (the worst-quality unprocessed neighbour), marking it processed.  The same
+// loop then continues over the fixed vertices, which places the ones the
+// interior loop never reaches (Theorem 1 misses a fixed vertex whose
+// neighbours are all fixed and never walked onto).
+std::vector<int32_t> order_rdr(const Mesh &M, const double *q) {
+    auto less = [q](int32_t a, int32_t b) { return q[a] < q[b] || (q[a] == q[b] && a < b); };
+    std::vector<int32_t> out;
+    out.reserve(size_t(M.n));
+    std::vector<uint8_t> processed(size_t(M.n), 0), placed(size_t(M.n), 0);
+    std::vector<int32_t> cur;
+    auto place = [&](int32_t v) {
+        if (!placed[v]) {
+            placed[v] = 1;
+            out.push_back(v);
+        }
+    };
+    auto unprocessed_neighbours = [&](int32_t w) {
+        cur.clear();
+        for (int64_t j = M.adj_ptr0[w]; j < M.adj_ptr0[w + 1]; ++j)
+            if (!processed[M.adj0[j]]) cur.push_back(M.adj0[j]);
+        std::sort(cur.begin(), cur.end(), less);
+    };
+    auto start_from = [&](int32_t i) {
+        if (processed[i]) return;
+        place(i);
+        processed[i] = 1;
+        unprocessed_neighbours(i);
+        while (!cur.empty()) {
+            for (int32_t u : cur) place(u);
+            const int32_t w = cur[0];
+            processed[w] = 1;
+            unprocessed_neighbours(w);
+        }
+    };
+    std::vector<int32_t> seeds;
+    for (int32_t mi = 0; mi < M.n_mesh; ++mi) {
+        const int32_t vb = int32_t(M.v_off[mi]), ve = int32_t(M.v_off[mi + 1]);
+        for (int pass = 0; pass < 2; ++pass) {
+            seeds.clear();
+            for (int32_t v = vb; v < ve; ++v)
+                if ((M.fixed0[v] != 0) == (pass == 1)) seeds.push_back(v);
+            std::sort(seeds.begin(), seeds.end(), less);
+            for (int32_t i : seeds) start_from(i);
+        }
+    }
+    return out;
+}
+
+namespace {
+// SplitMix64 (Steele, Lea, Flood 2014): Weyl sequence plus a mixing function.
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+}  // namespace
+
+// Fisher-Yates from the identity: for i = size-1 down to 1, swap element i
+// with element next() mod (i+1).  Mesh i of a batch uses seed + i.
+std::vector<int32_t> order_random(const Mesh &M, uint64_t seed) {
+    std::vector<int32_t> out(static_cast<size_t>(M.n));
+    for (int32_t mi = 0; mi < M.n_mesh; ++mi) {
+        const int64_t vb = M.v_off[mi], ve = M.v_off[mi + 1];
+        int32_t *p = out.data() + vb;
+        const int64_t sz = ve - vb;
+        for (int64_t i = 0; i < sz; ++i) p[i] = int32_t(vb + i);
+        SplitMix64 g{seed + uint64_t(mi)};
+        for (int64_t i = sz - 1; i >= 1; --i) {
+            const uint64_t j = g.next() % uint64_t(i + 1);
+            std::swap(p[i], p[j]);
+        }
+    }
+    return out;
+}
+
+// Apply an ordering: rebuild every current-label array from the input ones.
+// Triangles are relabelled and sorted by (smallest new vertex id, input
+// index), which keeps the quality pass's gathers local under any ordering.
+void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
+    const int32_t n = M.n;
+    std::vector<int32_t> old2new(static_cast<size_t>(n), -1);
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t v = new2old[k];
+        if (v < 0 || v >= n || old2new[v] != -1) fail(LMS_ERR_ARG, "ordering is not a permutation");
+        old2new[v] = k;
+    }
+    std::vector<int32_t> row_ptr(size_t(n) + 1), col;
+    std::vector<uint8_t> fx(static_cast<size_t>(n));
+    std::vector<int32_t> color(static_cast<size_t>(n));
+    int64_t nnz = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t v = new2old[k];
+        fx[k] = M.fixed0[v];
+        color[k] = M.color0[v];
+        if (!fx[k]) nnz += M.adj_ptr0[v + 1] - M.adj_ptr0[v];
+        row_ptr[k + 1] = int32_t(nnz);
+    }
+    resize_or_fail(col, size_t(nnz));
+    for (int32_t k = 0; k < n; ++k) {
+        if (fx[k]) continue;
+        const int32_t v = new2old[k];
+        int32_t *dst = col.data() + row_ptr[k];
+        int64_t d = 0;
+        for (int64_t j = M.adj_ptr0[v]; j < M.adj_ptr0[v + 1]; ++j) dst[d++] = old2new[M.adj0[j]];
+        std::sort(dst, dst + d);
+    }
+
+    std::vector<int32_t> color_ptr(size_t(M.n_colors) + 1, 0), color_list;
+    for (int32_t k = 0; k < n; ++k)
+        if (color[k] >= 0) color_ptr[color[k] + 1]++;
+    for (int32_t c = 0; c < M.n_colors; ++c) color_ptr[c + 1] += color_ptr[c];
+    color_list.resize(size_t(color_ptr[M.n_colors]));
+    {
+        std::vector<int32_t> fill(color_ptr.begin(), color_ptr.end() - 1);
+        for (int32_t k = 0; k < n; ++k)
+            if (color[k] >= 0) color_list[fill[color[k]]++] = k;
+    }
+
+    // triangles: counting sort by smallest new id, stable in input index
+    const int64_t T = M.T;
+    std::vector<int64_t> bucket(size_t(n) + 1, 0);
+    std::vector<int32_t> key(static_cast<size_t>(T));
+    for (int64_t t = 0; t < T; ++t) {
+        const int32_t a = old2new[M.tri0[3 * t]], b = old2new[M.tri0[3 * t + 1]], c = old2new[M.tri0[3 * t + 2]];
+        key[t] = std::min(a, std::min(b, c));
+        bucket[key[t] + 1]++;
+    }
+    for (int32_t k = 0; k < n; ++k) bucket[k + 1] += bucket[k];
+    std::vector<int64_t> torder(static_cast<size_t>(T));
+    for (int64_t t = 0; t < T; ++t) torder[bucket[key[t]]++] = t;
+    std::vector<int32_t> ta(static_cast<size_t>(T)), tb(static_cast<size_t>(T)), tc(static_cast<size_t>(T)),
+        tmesh(static_cast<size_t>(T));
+    std::vector<double> tw(static_cast<size_t>(T));
+    for (int64_t i = 0; i < T; ++i) {
+        const int64_t t = torder[i];
+        const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
+        ta[i] = old2new[a];
+        tb[i] = old2new[b];
+        tc[i] = old2new[c];
+        // weight of q_t in the global mean: (1/|V|) sum over its corners of
+        // 1/|T(v)| (the 1/|V| is applied after the sum)
+        tw[i] = 1.0 / double(M.tcount0[a]) + 1.0 / double(M.tcount0[b]) + 1.0 / double(M.tcount0[c]);
+        // mesh index: meshes own contiguous triangle ranges in input order
+        tmesh[i] = int32_t(std::upper_bound(M.t_off.begin(), M.t_off.end(), t) - M.t_off.begin() - 1);
+    }
+    std::vector<int32_t> vt_ptr(size_t(n) + 1, 0), vt(static_cast<size_t>(3 * T));
+    for (int64_t i = 0; i < T; ++i) {
+        vt_ptr[ta[i] + 1]++;
+        vt_ptr[tb[i] + 1]++;
+        vt_ptr[tc[i] + 1]++;
+    }
+    for (int32_t k = 0; k < n; ++k) vt_ptr[k + 1] += vt_ptr[k];
+    {
+        std::vector<int32_t> fill(vt_ptr.begin(), vt_ptr.end() - 1);
+        for (int64_t i = 0; i < T; ++i) {
+            vt[fill[ta[i]]++] = int32_t(i);
+            vt[fill[tb[i]]++] = int32_t(i);
+            vt[fill[tc[i]]++] = int32_t(i);
+        }
+    }
+
+    M.ordering = kind;
+    M.new2old = std::move(new2old);
+    M.old2new = std::move(old2new);
+    M.row_ptr = std::move(row_ptr);
+    M.col = std::move(col);
+    M.fixed = std::move(fx);
+    M.color = std::move(color);
+    M.color_ptr = std::move(color_ptr);
+    M.color_list = std::move(color_list);
+    M.ta = std::move(ta);
+    M.tb = std::move(tb);
+    M.tc = std::move(tc);
+    M.tw = std::move(tw);
+    M.tmesh = std::move(tmesh);
+    M.vt_ptr = std::move(vt_ptr);
+    M.vt = std::move(vt);
+    M.version++;
+}
+
+}  // namespace lms

@@ -1,0 +1,91 @@
+// Internal state of a mesh handle, shared by the host logic (lms_host.cpp)
+// and the device runtime (lms_device.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "lms.h"
+
+namespace lms {
+
+// Error carried from the internals to the C boundary.
+struct Error {
+    lms_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(lms_status code, const std::string &msg);
+
+struct DeviceState;  // defined in lms_device.hip
+void destroy_device_state(DeviceState *d);
+
+struct DeviceDeleter {
+    void operator()(DeviceState *d) const { destroy_device_state(d); }
+};
+
+// Everything the host knows about a mesh.  Arrays suffixed 0 are in INPUT
+// labels and never change after the build; the rest follow the current
+// ordering and are rebuilt by relabel().
+struct Mesh {
+    // ---- input labelling ----
+    int32_t n = 0;
+    int64_t T = 0;
+    std::vector<int32_t> tri0;              // 3T
+    std::vector<uint8_t> fixed0;            // n
+    std::vector<int64_t> adj_ptr0;          // n+1, full adjacency
+    std::vector<int32_t> adj0;              // ascending neighbours
+    std::vector<int32_t> tcount0;           // triangles per vertex
+    std::vector<int64_t> vt_ptr0;           // vertex -> triangles (ascending triangle index)
+    std::vector<int32_t> vt0;
+    std::vector<int32_t> color0;            // -1 for fixed vertices
+    int32_t n_colors = 0;
+    int32_t n_free = 0;
+    int32_t max_degree = 0;
+    // batched layout (n_mesh == 1 for a plain mesh)
+    int32_t n_mesh = 1;
+    std::vector<int64_t> v_off, t_off;      // n_mesh+1 each
+
+    // ---- current labelling ----
+    lms_ordering ordering = LMS_ORI;
+    std::vector<int32_t> new2old, old2new;
+    std::vector<int32_t> row_ptr;           // n+1, smoothing adjacency
+    std::vector<int32_t> col;               // nnz
+    std::vector<uint8_t> fixed;             // n
+    std::vector<int32_t> color;             // n
+    std::vector<int32_t> color_ptr;         // n_colors+1
+    std::vector<int32_t> color_list;        // free vertices grouped by colour, ascending
+    std::vector<int32_t> ta, tb, tc;        // triangles (current labels), sorted for locality
+    std::vector<double> tw;                 // per-triangle weight of the global mean
+    std::vector<int32_t> tmesh;             // mesh index of each triangle (current order)
+    std::vector<int32_t> vt_ptr, vt;        // vertex -> triangles in current labels/order
+
+    // generation counter: bumped whenever the current labelling changes so
+    // that device copies and captured graphs are refreshed
+    uint64_t version = 0;
+
+    std::unique_ptr<DeviceState, DeviceDeleter> dev;
+};
+
+// ---- host logic (lms_host.cpp) ----
+void build_mesh(Mesh &M, int32_t n, int64_t T, const int32_t *tri, const uint8_t *fixed,
+                int32_t n_mesh, const int64_t *v_off, const int64_t *t_off);
+void vertex_quality_host(const Mesh &M, const double *x, const double *y, double *q);
+std::vector<int32_t> order_bfs(const Mesh &M);
+std::vector<int32_t> order_rdr(const Mesh &M, const double *q);
+std::vector<int32_t> order_random(const Mesh &M, uint64_t seed);
+void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old);
+
+// ---- device runtime (lms_device.hip) ----
+void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,
+                 lms_precision p, int inverse, void *stream);
+void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,
+               lms_precision p, void *stream);
+void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p,
+                lms_scheme s, const lms_smooth_opts &o, void *stream, lms_smooth_result &r);
+void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global,
+                 double *q_vertex, double *q_mesh, void *stream);
+
+}  // namespace lms
