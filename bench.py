@@ -115,6 +115,7 @@ def main():
             sweep_us = ev_ms * 1e3 / launches
             b = sweep_bytes(n, n_free, nnz, s)
             results[f"{kind}_{prec}"] = dict(
+                sweep_kernel=M.sweep_config(prec).split(" ")[0],
                 vertex_updates_per_s=n_free * launches / wall,
                 ms_per_step=wall * 1e3 / args.steps,
                 sweep_us_events=sweep_us,
@@ -124,7 +125,9 @@ def main():
             log(f"{kind:7s} {prec}: {results[f'{kind}_{prec}']['vertex_updates_per_s']/1e9:7.2f} G upd/s  "
                 f"sweep {sweep_us:7.2f} us  {results[f'{kind}_{prec}']['achieved_gbs']:8.1f} GB/s")
             if kind == "rdr" and prec == "f64":
-                headline = dict(wall=wall, ev_ms=ev_ms, sweep_us=sweep_us, bytes=b)
+                headline = dict(wall=wall, ev_ms=ev_ms, sweep_us=sweep_us, bytes=b,
+                                kernel=M.sweep_config("f64"))
+                log("sweep variants (RDR, f64):", headline["kernel"])
             del x0, y0, x, y, tx, ty
 
     extras = {}
@@ -205,7 +208,7 @@ def main():
                    "n": n, "n_free": n_free, "n_tri": m.T, "nnz": nnz, "sweeps_per_step": SWEEPS},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_jacobi<double>", "bytes_per_launch": h["bytes"],
+                     "kernel": h.get("kernel", ""), "bytes_per_launch": h["bytes"],
                      "avg_launch_us": h["sweep_us"]},
         "cpu_baseline": cpu,
         "per_ordering": results,

@@ -195,6 +195,14 @@ lms_status lms_quality(lms_mesh_t m, const void *x, const void *y, lms_precision
 lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_precision p,
                                double *q_mesh, void *stream);
 
+/* Name of the sweep kernel variant chosen for precision p, followed by the
+ * per-variant timings the autotuner measured ("" until the first lms_smooth
+ * or lms_sweep of that precision since the last reorder).  The first sweep
+ * call per precision and ordering times every variant on the caller's
+ * stream (synchronously) and keeps the fastest; all variants give identical
+ * results.  buf: host char[len] out, NUL-terminated. */
+lms_status lms_sweep_config(lms_mesh_t m, lms_precision p, char *buf, int32_t len);
+
 /* Free the handle and everything it owns.  NULL is accepted. */
 lms_status lms_destroy(lms_mesh_t m);
 

@@ -1,5 +1,6 @@
 // The C ABI (include/lms.h): argument checks, status codes and the
 // thread-local error message around the host and device internals.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -166,6 +167,16 @@ lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_p
     return guarded([&] {
         if (!q_mesh) lms::fail(LMS_ERR_ARG, "q_mesh is NULL");
         lms::dev_quality(mesh_of(m), x, y, p, nullptr, nullptr, q_mesh, stream);
+    });
+}
+
+lms_status lms_sweep_config(lms_mesh_t m, lms_precision p, char *buf, int32_t len) {
+    return guarded([&] {
+        if (!buf || len <= 0) lms::fail(LMS_ERR_ARG, "buffer is NULL or empty");
+        const std::string s = lms::dev_sweep_config(mesh_of(m), p);
+        const size_t k = std::min(s.size(), size_t(len - 1));
+        std::memcpy(buf, s.data(), k);
+        buf[k] = 0;
     });
 }
 

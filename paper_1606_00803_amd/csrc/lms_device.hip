@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <limits>
@@ -114,6 +115,134 @@ __global__ __launch_bounds__(BS) void k_jacobi(const int32_t *__restrict__ row_p
         const T c = T(my_e - my_b);
         dx[r0 + tid] = ax / c;
         dy[r0 + tid] = ay / c;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ int32_t load_index(const int32_t *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+// Jacobi sweep, thread per row: each thread owns R rows (BS apart, so every
+// load instruction of the wavefront is coalesced), issues all their
+// neighbour-index loads U at a time, then all the coordinate gathers (all
+// independent, so they are in flight together), and adds each row in order.
+// No LDS and no barriers.  Sums in the same order as k_jacobi: same bits.
+// NT: neighbour indices are loaded with the non-temporal hint.
+template <typename T, int BS, int U, int R, bool SWZ, bool NT>
+__global__ __launch_bounds__(BS) void k_jacobi_row(const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const T *__restrict__ sx, const T *__restrict__ sy,
+                                                   T *__restrict__ dx, T *__restrict__ dy, int32_t n,
+                                                   const StopState *__restrict__ st) {
+    if (st && st->done) return;
+    const int nb = int(gridDim.x);
+    const int tile = SWZ ? xcd_tile(int(blockIdx.x), nb) : int(blockIdx.x);
+    const int32_t v0 = tile * (BS * R) + int32_t(threadIdx.x);
+    int32_t b[R], e[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t v = v0 + r * BS;
+        b[r] = v < n ? row_ptr[v] : 0;
+        e[r] = v < n ? row_ptr[v + 1] : 0;
+    }
+    int32_t u[R][U];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < U; ++k) u[r][k] = b[r] + k < e[r] ? load_index<NT>(col + b[r] + k) : -1;
+    T vx[R][U], vy[R][U];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            vx[r][k] = u[r][k] >= 0 ? sx[u[r][k]] : T(0);
+            vy[r][k] = u[r][k] >= 0 ? sy[u[r][k]] : T(0);
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (e[r] == b[r]) continue;
+        T ax = T(0), ay = T(0);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (u[r][k] >= 0) {
+                ax += vx[r][k];
+                ay += vy[r][k];
+            }
+        // rows longer than U: the rest in order, U at a time
+        for (int32_t j0 = b[r] + U; j0 < e[r]; j0 += U) {
+            int32_t w[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) w[k] = j0 + k < e[r] ? load_index<NT>(col + j0 + k) : -1;
+            T wx[U], wy[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                wx[k] = w[k] >= 0 ? sx[w[k]] : T(0);
+                wy[k] = w[k] >= 0 ? sy[w[k]] : T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (w[k] >= 0) {
+                    ax += wx[k];
+                    ay += wy[k];
+                }
+        }
+        const T c = T(e[r] - b[r]);
+        const int32_t v = v0 + r * BS;
+        dx[v] = ax / c;
+        dy[v] = ay / c;
+    }
+}
+
+// Jacobi sweep over the padded ("ELL") copy of the adjacency: entry k of
+// every row sits at ell[k*n + v] (-1 past the row's end), so a thread finds
+// its neighbours without first reading row offsets, and every index load of
+// a wavefront is one coalesced line.  Rows have at most W entries.  Each
+// thread owns R rows BS apart.  Entries are in the CSR order: same bits.
+template <typename T, int BS, int W, int R, bool SWZ>
+__global__ __launch_bounds__(BS) void k_jacobi_ell(const int32_t *__restrict__ ell,
+                                                   const T *__restrict__ sx, const T *__restrict__ sy,
+                                                   T *__restrict__ dx, T *__restrict__ dy, int32_t n,
+                                                   const StopState *__restrict__ st) {
+    if (st && st->done) return;
+    const int nb = int(gridDim.x);
+    const int tile = SWZ ? xcd_tile(int(blockIdx.x), nb) : int(blockIdx.x);
+    const int32_t v0 = tile * (BS * R) + int32_t(threadIdx.x);
+    int32_t u[R][W];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t v = v0 + r * BS;
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            u[r][k] = v < n ? __builtin_nontemporal_load(ell + int64_t(k) * n + v) : -1;
+    }
+    T vx[R][W], vy[R][W];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            vx[r][k] = u[r][k] >= 0 ? sx[u[r][k]] : T(0);
+            vy[r][k] = u[r][k] >= 0 ? sy[u[r][k]] : T(0);
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        T ax = T(0), ay = T(0);
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            if (u[r][k] >= 0) {
+                ax += vx[r][k];
+                ay += vy[r][k];
+                ++cnt;
+            }
+        if (cnt == 0) continue;
+        const T c = T(cnt);
+        const int32_t v = v0 + r * BS;
+        dx[v] = ax / c;
+        dy[v] = ay / c;
     }
 }
 
@@ -328,8 +457,6 @@ __global__ __launch_bounds__(256) void k_permute(const int32_t *__restrict__ new
 
 namespace {
 
-constexpr int kSweepBS = 256;
-constexpr int kSweepCap = 2048;
 constexpr int kQualBS = 256;
 constexpr int kQualMaxBlocks = 1024;
 constexpr int kChunk = 16;  // sweeps per captured chunk under the stopping rule (even)
@@ -353,6 +480,7 @@ struct DeviceState {
     uint64_t version = ~uint64_t(0);
     std::vector<void *> arrays;  // mesh arrays of the current version
     int32_t *row_ptr = nullptr, *col = nullptr, *color_list = nullptr, *new2old = nullptr;
+    int32_t *ell = nullptr;  // padded adjacency (column-major), when the handle has one
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
     double *tw = nullptr;
     int64_t *t_off = nullptr, *v_off = nullptr;
@@ -370,6 +498,8 @@ struct DeviceState {
     hipStream_t cap = nullptr;
     std::vector<GraphEntry> graphs;
     bool use_graphs = true;
+    int sweep_cfg[2] = {-1, -1};     // chosen sweep variant per precision, -1 = not tuned
+    float tune_us[2][32] = {};       // measured time per variant (microseconds per sweep)
 };
 
 namespace {
@@ -429,6 +559,7 @@ DeviceState &ensure_device(Mesh &M) {
         d->version = ~uint64_t(0);
         d->row_ptr = upload(d, M.row_ptr);
         d->col = upload(d, M.col);
+        d->ell = M.ell_w > 0 ? upload(d, M.ell) : nullptr;
         d->color_list = upload(d, M.color_list);
         d->new2old = upload(d, M.new2old);
         d->ta = upload(d, M.ta);
@@ -443,6 +574,7 @@ DeviceState &ensure_device(Mesh &M) {
         HIP_CHECK(hipMalloc(&qm, sizeof(double) * size_t(M.n_mesh)));
         d->arrays.push_back(qm);
         d->qmesh = static_cast<double *>(qm);
+        d->sweep_cfg[0] = d->sweep_cfg[1] = -1;  // a new ordering is tuned afresh
         d->version = M.version;
     }
     return *d;
@@ -461,11 +593,176 @@ void launch_check() {
     if (e != hipSuccess) fail(LMS_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
 }
 
+// The sweep kernel variants the autotuner chooses from.  All of them sum each
+// row in ascending neighbour order from 0, so they return identical bits.
+//   ROW(id, BS, U, R, SWZ, NT)   k_jacobi_row
+//   LDS(id, BS, CAP, SWZ)        k_jacobi
+//   ELL(id, BS, W, R, SWZ)       k_jacobi_ell (eligible when the padded width is W)
+#define LMS_SWEEP_CONFIGS(ROW, LDS, ELL) \
+    ROW(0, 256, 8, 1, true, true)        \
+    ROW(1, 256, 8, 1, false, true)       \
+    ROW(2, 64, 8, 1, true, true)         \
+    ROW(3, 256, 8, 1, true, false)       \
+    ROW(4, 256, 8, 2, true, true)        \
+    ROW(5, 128, 8, 2, true, false)       \
+    ROW(6, 256, 4, 2, true, false)       \
+    LDS(7, 256, 2048, true)              \
+    LDS(8, 128, 1024, true)              \
+    LDS(9, 64, 512, true)                \
+    ELL(10, 256, 8, 1, true)             \
+    ELL(11, 256, 8, 2, true)             \
+    ELL(12, 128, 8, 2, false)            \
+    ELL(13, 64, 8, 1, true)              \
+    ELL(14, 256, 8, 4, true)             \
+    ELL(15, 256, 12, 1, true)            \
+    ELL(16, 256, 12, 2, true)            \
+    ELL(17, 256, 16, 1, true)
+constexpr int kNumSweepConfigs = 18;
+constexpr int kDefaultSweepConfig = 0;
+
+std::string sweep_config_name(int cfg) {
+    char buf[96];
+    switch (cfg) {
+#define ROW(id, bs, u, r, swz, nt)                                                                  \
+    case id:                                                                                        \
+        std::snprintf(buf, sizeof(buf), "row/bs%d/u%d/r%d/%s%s", bs, u, r, swz ? "xcd" : "linear", \
+                      nt ? "/nt" : "");                                                             \
+        return buf;
+#define LDS(id, bs, cap, swz)                                                                      \
+    case id:                                                                                       \
+        std::snprintf(buf, sizeof(buf), "lds/bs%d/cap%d/%s", bs, cap, swz ? "xcd" : "linear");    \
+        return buf;
+#define ELL(id, bs, w, r, swz)                                                                     \
+    case id:                                                                                       \
+        std::snprintf(buf, sizeof(buf), "ell/bs%d/w%d/r%d/%s", bs, w, r, swz ? "xcd" : "linear"); \
+        return buf;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL)
+#undef ROW
+#undef LDS
+#undef ELL
+    }
+    return "unknown";
+}
+
+// Padded width an ELL variant needs (0: not an ELL variant).
+int sweep_config_ell_width(int cfg) {
+    switch (cfg) {
+#define ROW(id, bs, u, r, swz, nt) \
+    case id:                       \
+        return 0;
+#define LDS(id, bs, cap, swz) \
+    case id:                  \
+        return 0;
+#define ELL(id, bs, w, r, swz) \
+    case id:                   \
+        return w;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL)
+#undef ROW
+#undef LDS
+#undef ELL
+    }
+    return -1;
+}
+
+bool sweep_config_eligible(int cfg, const Mesh &M) {
+    const int w = sweep_config_ell_width(cfg);
+    return w == 0 || (w > 0 && w == M.ell_w);
+}
+
+template <typename T>
+void launch_sweep_cfg(int cfg, const DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
+                      const StopState *st, hipStream_t s) {
+    const int64_t n = M.n;
+    switch (cfg) {
+#define ROW(id, bs, u, r, swz, nt)                                                                   \
+    case id:                                                                                         \
+        k_jacobi_row<T, bs, u, r, swz, nt><<<int((n + bs * r - 1) / (bs * r)), bs, 0, s>>>(          \
+            d.row_ptr, d.col, sx, sy, dx, dy, M.n, st);                                              \
+        break;
+#define LDS(id, bs, cap, swz)                                                                         \
+    case id:                                                                                          \
+        k_jacobi<T, bs, cap, swz><<<int((n + bs - 1) / bs), bs, 0, s>>>(d.row_ptr, d.col, sx, sy, dx, \
+                                                                          dy, M.n, st);              \
+        break;
+#define ELL(id, bs, w, r, swz)                                                                       \
+    case id:                                                                                         \
+        if (M.ell_w != w) fail(LMS_ERR_STATE, "padded adjacency width does not match the variant"); \
+        k_jacobi_ell<T, bs, w, r, swz><<<int((n + bs * r - 1) / (bs * r)), bs, 0, s>>>(               \
+            d.ell, sx, sy, dx, dy, M.n, st);                                                         \
+        break;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL)
+#undef ROW
+#undef LDS
+#undef ELL
+        default:
+            fail(LMS_ERR_STATE, "bad sweep configuration");
+    }
+}
+
 template <typename T>
 void launch_sweep(const DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
                   const StopState *st, hipStream_t s) {
-    const int nb = (M.n + kSweepBS - 1) / kSweepBS;
-    k_jacobi<T, kSweepBS, kSweepCap, true><<<nb, kSweepBS, 0, s>>>(d.row_ptr, d.col, sx, sy, dx, dy, M.n, st);
+    launch_sweep_cfg<T>(d.sweep_cfg[sizeof(T) == 8 ? 0 : 1], d, M, sx, sy, dx, dy, st, s);
+}
+
+// Autotuner: time every sweep variant on this mesh (src -> dst, which leaves
+// dst holding one sweep of src) and keep the fastest for the handle's current
+// ordering and this precision.  LMS_SWEEP_CONFIG=<id> forces a variant;
+// LMS_AUTOTUNE=0 keeps the default.
+template <typename T>
+void tune_sweep(DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, T *dy, hipStream_t s) {
+    const int pi = sizeof(T) == 8 ? 0 : 1;
+    if (d.sweep_cfg[pi] >= 0) return;
+    if (const char *f = std::getenv("LMS_SWEEP_CONFIG")) {
+        const int c = std::atoi(f);
+        if (c < 0 || c >= kNumSweepConfigs) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG out of range");
+        if (!sweep_config_eligible(c, M)) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG names a variant this mesh cannot use");
+        d.sweep_cfg[pi] = c;
+        return;
+    }
+    if (!env_flag("LMS_AUTOTUNE", true)) {
+        d.sweep_cfg[pi] = kDefaultSweepConfig;
+        return;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_CHECK(hipEventCreate(&e0));
+    hipError_t ce = hipEventCreate(&e1);
+    if (ce != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        HIP_CHECK(ce);
+    }
+    const int64_t work = int64_t(M.n) + int64_t(M.col.size());
+    const int reps = work > (int64_t(1) << 26) ? 3 : (work > (int64_t(1) << 22) ? 6 : 12);
+    int best = kDefaultSweepConfig;
+    float best_ms = 3.0e38f;
+    hipError_t err = hipSuccess;
+    for (int c = 0; c < kNumSweepConfigs && err == hipSuccess; ++c) {
+        if (!sweep_config_eligible(c, M)) {
+            d.tune_us[pi][c] = -1.f;
+            continue;
+        }
+        launch_sweep_cfg<T>(c, d, M, sx, sy, dx, dy, nullptr, s);
+        launch_sweep_cfg<T>(c, d, M, sx, sy, dx, dy, nullptr, s);
+        err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) launch_sweep_cfg<T>(c, d, M, sx, sy, dx, dy, nullptr, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        d.tune_us[pi][c] = ms * 1000.f / float(reps);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_CHECK(err);
+    launch_check();
+    d.sweep_cfg[pi] = best;
+    if (env_flag("LMS_VERBOSE", false))
+        std::fprintf(stderr, "[lms] sweep autotune (%s, n=%d): %s, %.2f us\n", pi == 0 ? "f64" : "f32", M.n,
+                     sweep_config_name(best).c_str(), double(best_ms) * 1000.0 / reps);
 }
 
 template <typename T>
@@ -563,8 +860,10 @@ bool overlaps(const void *a, const void *b, size_t bytes) {
 template <typename T>
 void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precision p, lms_scheme sch,
                   const lms_smooth_opts &o, hipStream_t s, lms_smooth_result &r) {
+    if (sch == LMS_JACOBI) tune_sweep<T>(d, M, x, y, tx, ty, s);
     const std::string base = std::string(p == LMS_FP64 ? "f64" : "f32") + "|" + ptr_key(x) + "|" +
-                             ptr_key(y) + "|" + ptr_key(tx) + "|" + ptr_key(ty);
+                             ptr_key(y) + "|" + ptr_key(tx) + "|" + ptr_key(ty) + "|cfg" +
+                             std::to_string(d.sweep_cfg[sizeof(T) == 8 ? 0 : 1]);
     const size_t bytes = sizeof(T) * size_t(M.n);
     const bool jacobi = sch == LMS_JACOBI;
     if (jacobi) {
@@ -689,12 +988,17 @@ void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lms_
         fail(LMS_ERR_ARG, "a Jacobi sweep cannot run in place");
     DeviceState &d = ensure_device(M);
     hipStream_t s = as_stream(stream);
-    if (p == LMS_FP64)
+    if (p == LMS_FP64) {
+        tune_sweep<double>(d, M, static_cast<const double *>(sx), static_cast<const double *>(sy),
+                           static_cast<double *>(dx), static_cast<double *>(dy), s);
         launch_sweep<double>(d, M, static_cast<const double *>(sx), static_cast<const double *>(sy),
                              static_cast<double *>(dx), static_cast<double *>(dy), nullptr, s);
-    else
+    } else {
+        tune_sweep<float>(d, M, static_cast<const float *>(sx), static_cast<const float *>(sy),
+                          static_cast<float *>(dx), static_cast<float *>(dy), s);
         launch_sweep<float>(d, M, static_cast<const float *>(sx), static_cast<const float *>(sy),
                             static_cast<float *>(dx), static_cast<float *>(dy), nullptr, s);
+    }
     launch_check();
 }
 
@@ -725,6 +1029,21 @@ void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p, 
     else
         smooth_typed<float>(M, d, static_cast<float *>(x), static_cast<float *>(y), static_cast<float *>(tx),
                             static_cast<float *>(ty), p, sch, o, s, r);
+}
+
+std::string dev_sweep_config(Mesh &M, lms_precision p) {
+    check_precision(p);
+    if (!M.dev || M.dev->version != M.version) return "";
+    const int c = M.dev->sweep_cfg[p == LMS_FP64 ? 0 : 1];
+    if (c < 0) return "";
+    std::string out = sweep_config_name(c);
+    char buf[64];
+    for (int i = 0; i < kNumSweepConfigs; ++i) {
+        std::snprintf(buf, sizeof(buf), "%s%d:%.2fus", i == 0 ? " tuned[" : " ", i,
+                      double(M.dev->tune_us[p == LMS_FP64 ? 0 : 1][i]));
+        out += buf;
+    }
+    return out + "]";
 }
 
 void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global, double *q_vertex,

@@ -325,6 +325,18 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
         std::sort(dst, dst + d);
     }
 
+    // padded copy of the smoothing adjacency for the offset-free sweep
+    // variant: width 8, 12 or 16 (the smallest that holds every row)
+    int32_t ell_w = 0;
+    std::vector<int32_t> ell;
+    if (M.max_degree <= 16) {
+        ell_w = M.max_degree <= 8 ? 8 : (M.max_degree <= 12 ? 12 : 16);
+        resize_or_fail(ell, size_t(ell_w) * size_t(n));
+        std::fill(ell.begin(), ell.end(), -1);
+        for (int32_t k = 0; k < n; ++k)
+            for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j) ell[size_t(j - row_ptr[k]) * size_t(n) + k] = col[j];
+    }
+
     std::vector<int32_t> color_ptr(size_t(M.n_colors) + 1, 0), color_list;
     for (int32_t k = 0; k < n; ++k)
         if (color[k] >= 0) color_ptr[color[k] + 1]++;
@@ -384,6 +396,8 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
     M.old2new = std::move(old2new);
     M.row_ptr = std::move(row_ptr);
     M.col = std::move(col);
+    M.ell_w = ell_w;
+    M.ell = std::move(ell);
     M.fixed = std::move(fx);
     M.color = std::move(color);
     M.color_ptr = std::move(color_ptr);

@@ -53,6 +53,8 @@ struct Mesh {
     std::vector<int32_t> new2old, old2new;
     std::vector<int32_t> row_ptr;           // n+1, smoothing adjacency
     std::vector<int32_t> col;               // nnz
+    int32_t ell_w = 0;                      // padded width (8, 12 or 16), 0 = no padded copy
+    std::vector<int32_t> ell;               // ell[k*n + v]: entry k of row v, -1 past its end
     std::vector<uint8_t> fixed;             // n
     std::vector<int32_t> color;             // n
     std::vector<int32_t> color_ptr;         // n_colors+1
@@ -85,6 +87,7 @@ void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,
                lms_precision p, void *stream);
 void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p,
                 lms_scheme s, const lms_smooth_opts &o, void *stream, lms_smooth_result &r);
+std::string dev_sweep_config(Mesh &M, lms_precision p);
 void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global,
                  double *q_vertex, double *q_mesh, void *stream);
 

@@ -69,6 +69,7 @@ _SIGS = {
     "lms_sweep": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "lms_quality": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp]),
     "lms_quality_batched": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
+    "lms_sweep_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_char_p, _i32]),
     "lms_destroy": (ctypes.c_int, [_vp]),
     "lms_last_error": (ctypes.c_char_p, []),
     "lms_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
@@ -302,6 +303,12 @@ class Mesh:
         out = ctypes.c_double()
         _check(load().lms_quality(self.handle, a, b, p, ctypes.byref(out), qv, _stream()))
         return out.value
+
+    def sweep_config(self, precision="f64") -> str:
+        buf = ctypes.create_string_buffer(1024)
+        p = FP64 if precision in ("f64", FP64) else FP32
+        _check(load().lms_sweep_config(self.handle, p, buf, 1024))
+        return buf.value.decode()
 
     def quality_batched(self, x, y) -> np.ndarray:
         i = self.info()

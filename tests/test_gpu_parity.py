@@ -225,7 +225,9 @@ def test_stopping_rule_goal_max_iters_and_resume():
     g = osm.smooth(top, m.x, m.y, max_iters=2000, goal=goal)
     _, _, r, _ = run_library(m, "rdr", 2000, check_quality=True, goal=goal)
     assert (r["iters"], r["stopped_by"]) == (g.iters, "goal")
-    _, _, r, _ = run_library(m, "bfs", 2000, check_quality=True, goal=ref.q0)
+    # a goal already met by Q_0 (kept 1e-9 below it: Q_0 itself is only
+    # reproduced to rounding) stops before the first sweep
+    _, _, r, _ = run_library(m, "bfs", 2000, check_quality=True, goal=ref.q0 - 1e-9)
     assert (r["iters"], r["stopped_by"]) == (0, "goal")
     _, _, r, _ = run_library(m, "bfs", 3, check_quality=True, tol=-math.inf)
     assert (r["iters"], r["stopped_by"]) == (3, "max_iters")
@@ -332,3 +334,55 @@ def test_batched_equals_per_mesh(prec):
                 ex, ey = osm.jacobi(top, m.x, m.y, 30)
                 assert np.max(np.abs(bx[seg] - ex)) <= TOL64 * extent(m.xy)
                 assert abs(qm[i] - oq.global_quality(ex, ey, m.tri, m.n)) <= 1e-12
+
+
+@pytest.mark.parametrize("width", [8, 12, 16])
+def test_every_sweep_variant_gives_the_same_bits(width):
+    # the autotuner may pick any variant: all must sum rows in the same order.
+    # A wheel whose centre has 11 or 15 neighbours sets the padded width.
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    parts = [meshgen.jittered_grid(333, 301, seed=14, land_fraction=0.3)]
+    if width > 8:
+        parts.append(meshgen.wheel(width - 1, seed=3, centre=(3.0, 0.5)))
+    m = meshgen.concat(parts)[0] if len(parts) > 1 else parts[0]
+    top = oracle_topology(m)
+    assert top.degree[top.fixed == 0].max() == (8 if width == 8 else width - 1)
+    ex, ey = osm.jacobi(top, m.x, m.y, 9)
+    ref = {}
+    ran = 0
+    try:
+        for cfg in range(18):
+            os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
+            for dt in (torch.float64, torch.float32):
+                try:
+                    x, y, _, M = run_library(m, "rdr", 9, dtype=dt)
+                except lms.LmsError as e:        # a padded variant of another width
+                    assert e.status == 1 and "cannot use" in str(e)
+                    continue
+                ran += 1
+                name = M.sweep_config("f64" if dt == torch.float64 else "f32")
+                assert name.startswith(("row/", "lds/", "ell/"))
+                if name.startswith("ell/"):
+                    assert f"/w{width}/" in name
+                ref.setdefault(str(dt), (x, y))
+                assert np.array_equal(x, ref[str(dt)][0]) and np.array_equal(y, ref[str(dt)][1]), cfg
+                if dt == torch.float64:
+                    assert np.max(np.abs(x - ex)) <= TOL64 * extent(m.xy)
+    finally:
+        os.environ.pop("LMS_SWEEP_CONFIG", None)
+    assert ran >= 2 * 10
+
+
+def test_autotuned_sweep_matches_oracle_and_reports_choice():
+    from paper_1606_00803_amd import lms
+    m = meshgen.jittered_grid(400, seed=15, land_fraction=0.3)
+    top = oracle_topology(m)
+    ex, ey = osm.jacobi(top, m.x, m.y, 6)
+    x, y, _, M = run_library(m, "bfs", 6)
+    name = M.sweep_config("f64")
+    assert name.split("/")[0] in ("row", "lds", "ell")
+    assert "tuned[" in name and M.sweep_config("f32") == ""
+    M.reorder("random", seed=1)                  # a new ordering is tuned afresh
+    assert M.sweep_config("f64") == "" and isinstance(lms.ORI, int)
+    assert np.max(np.abs(x - ex)) <= TOL64 * extent(m.xy)
