@@ -1,26 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark: Laplacian mesh smoothing sweeps on one MI355X.
 
-Workload: the ocean-like mesh (1000 x 1000 jittered grid, ~30% of the cells
-cut out as disc-union holes, hole rims fixed; ~708k vertices, ~687k free),
-50 Jacobi sweeps per step (Eq. 1 applied to every free vertex), float64.
-The headline value is vertex-updates/s under the RDR ordering (Algorithm 2);
-the JSON line also carries every ordering (ORI, BFS, RDR, random) in float64
-and float32, the roofline of the sweep kernel, the multicolour and quality
-passes, host preprocessing times and the oracle's CPU rate.
+Default workload (the JSON line the metric is quoted on): the ocean-like mesh
+(1000 x 1000 jittered grid, ~30% of the cells cut out as disc-union holes,
+hole rims fixed; 708,312 vertices, 686,911 free), 50 Jacobi sweeps per step
+(Eq. 1 applied to every free vertex), float64.  The headline value is
+vertex-updates/s under the RDR ordering (Algorithm 2); the line also carries
+every ordering (ORI, BFS, RDR, random) in float64 and float32, the roofline
+of the sweep kernel, the multicolour and quality passes, a STREAM-copy
+reference, host preprocessing times and the oracle's CPU rate.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+    python bench.py --workload graded16m|batch512|graded64m   (other configs)
 
-A step is one lms_smooth call of 50 sweeps (one captured graph launch) on
-coordinates already resident in HBM; the timed region covers exactly
---steps steps bracketed by torch.cuda.synchronize().
+A step is one lms_smooth call of K sweeps (one captured graph launch) on
+coordinates already resident in HBM; the timed region covers exactly --steps
+steps bracketed by torch.cuda.synchronize().
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -30,9 +34,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-SWEEPS = 50
 ORDER_NAMES = ["ori", "bfs", "rdr", "random"]
 RANDOM_SEED = 1002
+METRIC = "vertex-updates/sec and % HBM roofline per ordering (ORI/BFS/RDR/random), FP64 vs FP32"
+COUNTERS_MD = os.path.join(ROOT, "profiles", "sweep_ocean_rdr_f64_counters.md")
+DEVICE_SRC = os.path.join(ROOT, "paper_1606_00803_amd", "csrc", "lms_device.hip")
 
 
 def log(*a):
@@ -45,175 +51,365 @@ def sweep_bytes(n, n_free, nnz, s):
     return 2 * s * n + 2 * s * n_free + 4 * (n + 1) + 4 * nnz
 
 
+def quality_bytes(n, T, s):
+    """Algorithmic bytes of one quality pass: three int32 corners and one
+    float64 weight per triangle, every coordinate pair once."""
+    return 20 * T + 2 * s * n
+
+
+def device_source_hash():
+    with open(DEVICE_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def counters_traffic(kernel_name):
+    """HBM traffic per launch from the committed counter summary, when it was
+    taken on the current kernel source and the same sweep variant."""
+    try:
+        text = open(COUNTERS_MD).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^- (\w+): (\S+)$", text, flags=re.M))
+    if fields.get("source_sha256") != device_source_hash():
+        return None
+    if fields.get("variant") != kernel_name:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream the library launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.s = torch.cuda.current_stream()
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.w0 = time.perf_counter()
+        self.e0.record(self.s)
+        return self
+
+    def __exit__(self, *a):
+        self.e1.record(self.s)
+        self.torch.cuda.synchronize()
+        self.wall = time.perf_counter() - self.w0
+        self.ms = self.e0.elapsed_time(self.e1)
+
+
+def stream_copy_gbs(torch, mbytes=2048):
+    """Achieved bandwidth of a plain device copy (read + write bytes / time)."""
+    n = mbytes * (1 << 20) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        b.copy_(a)
+    reps = 10
+    with Timer(torch) as t:
+        for _ in range(reps):
+            b.copy_(a)
+    del a, b
+    return 2 * n * 8 * reps / (t.ms * 1e-3) / 1e9
+
+
+def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
+    """Reorder, upload, time `steps` calls of `sweeps` sweeps.  Returns a dict."""
+    from paper_1606_00803_amd import lms  # noqa: F401
+    dt = torch.float64 if prec == "f64" else torch.float32
+    x0 = torch.as_tensor(m.x, dtype=dt, device="cuda")
+    y0 = torch.as_tensor(m.y, dtype=dt, device="cuda")
+    x = torch.empty_like(x0)
+    y = torch.empty_like(y0)
+    M.permute(x0, y0, x, y)
+    tx = torch.empty_like(x)
+    ty = torch.empty_like(y)
+    for _ in range(warmup):
+        M.smooth(x, y, tx, ty, scheme=scheme, max_iters=sweeps, check_quality=False)
+    with Timer(torch) as t:
+        for _ in range(steps):
+            M.smooth(x, y, tx, ty, scheme=scheme, max_iters=sweeps, check_quality=False)
+    info = M.info()
+    s = 8 if prec == "f64" else 4
+    b = sweep_bytes(info["n"], info["n_free"], info["nnz"], s)
+    launches = steps * sweeps
+    sweep_us = t.ms * 1e3 / launches
+    out = dict(sweep_kernel=M.sweep_config(prec).split(" ")[0] if scheme == "jacobi" else "colour",
+               vertex_updates_per_s=info["n_free"] * launches / t.wall,
+               ms_per_step=t.wall * 1e3 / steps, sweep_us_events=sweep_us,
+               achieved_gbs=b / (sweep_us * 1e-6) / 1e9,
+               frac_hbm=b / (sweep_us * 1e-6) / 1e9 / HBM_PEAK_GBS, bytes_per_sweep=b,
+               wall=t.wall, ev_ms=t.ms)
+    del x0, y0, tx, ty
+    return out, (x, y)
+
+
+def cpu_baseline(m, sweeps, budget_s=3.0):
+    from oracle import mesh as omesh
+    from oracle import smooth as osm
+    top = omesh.topology(m.n, m.tri)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    reps = 0
+    w0 = time.perf_counter()
+    while reps < 1 or time.perf_counter() - w0 < budget_s:
+        osm.jacobi(top, m.x, m.y, sweeps, threads=cores)
+        reps += 1
+    wall = time.perf_counter() - w0
+    free = int((top.fixed == 0).sum())
+    return dict(value=free * sweeps * reps / wall, unit="vertex-updates/s", cores=cores, kind="oracle",
+                sample=f"the full workload ({m.n} vertices, {sweeps} float64 Jacobi sweeps, ORI labels) "
+                       f"repeated {reps} times, OpenMP static schedule over {cores} threads"), top
+
+
+def result_line(value, steps, warmup, ms_per_step, dtype, config, roofline, cpu, **extra):
+    out = {"metric": METRIC, "value": value, "unit": "vertex-updates/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": config,
+           "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extra)
+    return out
+
+
+def roofline_of(r):
+    traffic = counters_traffic(r["sweep_kernel"])
+    return {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "sweep " + r["sweep_kernel"], "bytes_per_launch": r["bytes_per_sweep"],
+            "avg_launch_us": r["sweep_us_events"]}
+
+
+# ---------------------------------------------------------------- workloads
+
+def bench_ocean(torch, args):
+    import meshgen
+    from paper_1606_00803_amd import lms
+    SWEEPS = 50
+    t0 = time.perf_counter()
+    m = meshgen.ocean()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    t_csr = time.perf_counter() - t0
+    info = M.info()
+    log(f"ocean mesh n={info['n']} n_free={info['n_free']} T={m.T} nnz={info['nnz']} "
+        f"colours={info['n_colors']} gen={t_gen:.2f}s csr={t_csr:.2f}s")
+    if args.calibration_copy_mb:
+        # a copy of known size, for scaling the memory counters
+        a = torch.empty(args.calibration_copy_mb << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
+    results, reorder_s = {}, {}
+    for kind in [o for o in args.orderings.split(",") if o]:
+        t0 = time.perf_counter()
+        M.reorder(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)
+        reorder_s[kind] = time.perf_counter() - t0
+        for prec in ("f64", "f32"):
+            r, _ = run_fixed(torch, M, m, kind, prec, SWEEPS, args.steps, args.warmup)
+            results[f"{kind}_{prec}"] = r
+            log(f"{kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  sweep "
+                f"{r['sweep_us_events']:7.2f} us  {r['achieved_gbs']:8.1f} GB/s  [{r['sweep_kernel']}]")
+            if kind == "rdr" and prec == "f64":
+                log("sweep variants (RDR, f64):", M.sweep_config("f64"))
+    extras = {}
+    if not args.no_extras:
+        M.reorder("rdr", x0=m.x, y0=m.y)
+        r, (x, y) = run_fixed(torch, M, m, "rdr", "f64", SWEEPS, args.steps, 1, scheme="multicolor")
+        extras["multicolor_rdr_f64"] = {k: r[k] for k in ("vertex_updates_per_s", "sweep_us_events")}
+        extras["multicolor_rdr_f64"]["colour_passes_per_sweep"] = info["n_colors"]
+        M.quality(x, y)
+        with Timer(torch) as t:
+            for _ in range(args.steps):
+                M.quality(x, y)
+        qb = quality_bytes(info["n"], m.T, 8)
+        extras["quality_pass"] = dict(us_per_call_incl_host_sync=t.wall * 1e6 / args.steps,
+                                      algorithmic_bytes=qb)
+        x0 = torch.as_tensor(m.x, dtype=torch.float64, device="cuda")
+        y0 = torch.as_tensor(m.y, dtype=torch.float64, device="cuda")
+        M.permute(x0, y0, x, y)
+        with Timer(torch) as t:
+            rr = M.smooth(x, y, max_iters=2000, tol=5e-6)
+        extras["to_criterion_rdr_f64"] = dict(iters=rr["iters"], stopped_by=rr["stopped_by"], q0=rr["q0"],
+                                              q_final=rr["q_final"], seconds=t.wall)
+        extras["stream_copy_gbs"] = stream_copy_gbs(torch)
+        extras["host_seconds"] = dict(generate=t_gen, build_csr=t_csr,
+                                      **{f"reorder_{k}": v for k, v in reorder_s.items()})
+        g = {k: results.get(f"{k}_f64", {}).get("vertex_updates_per_s") for k in ORDER_NAMES}
+        if g.get("rdr") and g.get("ori") and g.get("bfs"):
+            # the paper's gain metric (T_algo - T_RDR) / T_algo, here on the GPU
+            extras["rdr_gain_f64"] = {a: 1.0 - g[a] / g["rdr"] for a in ("ori", "bfs", "random") if g.get(a)}
+        del x, y, x0, y0
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, _ = cpu_baseline(m, SWEEPS)
+        log(f"oracle on {cpu['cores']} host threads: {cpu['value'] / 1e9:.3f} G upd/s")
+    h = results.get("rdr_f64") or next(iter(results.values()))
+    return result_line(
+        h["vertex_updates_per_s"], args.steps, args.warmup, h["ms_per_step"], "f64",
+        {"workload": "ocean-like mesh: 1000x1000 jittered grid, ~30% disc-union holes, "
+                     f"{SWEEPS} Jacobi sweeps per step, RDR ordering, float64",
+         "n": info["n"], "n_free": info["n_free"], "n_tri": m.T, "nnz": info["nnz"],
+         "sweeps_per_step": SWEEPS, "mesh_sha256": meshgen.mesh_hash(m)},
+        roofline_of(h), cpu, per_ordering=strip(results), extras=extras)
+
+
+def strip(results):
+    return {k: {kk: vv for kk, vv in v.items() if kk not in ("wall", "ev_ms")} for k, v in results.items()}
+
+
+def bench_graded16m(torch, args):
+    import meshgen
+    from paper_1606_00803_amd import lms
+    SWEEPS = 100
+    t0 = time.perf_counter()
+    m = meshgen.graded16m()
+    t_gen = time.perf_counter() - t0
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    info = M.info()
+    log(f"graded mesh n={info['n']} n_free={info['n_free']} T={m.T} nnz={info['nnz']} gen={t_gen:.1f}s")
+    results, reorder_s, finals = {}, {}, {}
+    for kind in [o for o in args.orderings.split(",") if o in ("rdr", "ori", "bfs", "random")]:
+        t0 = time.perf_counter()
+        M.reorder(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)
+        reorder_s[kind] = time.perf_counter() - t0
+        for prec in ("f64", "f32"):
+            r, (x, y) = run_fixed(torch, M, m, kind, prec, SWEEPS, args.steps, args.warmup)
+            results[f"{kind}_{prec}"] = r
+            log(f"{kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  sweep "
+                f"{r['sweep_us_events']:8.2f} us  {r['achieved_gbs']:8.1f} GB/s  [{r['sweep_kernel']}]")
+            if kind == "rdr":
+                # one clean run of exactly SWEEPS sweeps from P_0 for the error metric
+                dt = torch.float64 if prec == "f64" else torch.float32
+                x0 = torch.as_tensor(m.x, dtype=dt, device="cuda")
+                y0 = torch.as_tensor(m.y, dtype=dt, device="cuda")
+                M.permute(x0, y0, x, y)
+                M.smooth(x, y, max_iters=SWEEPS, check_quality=False)
+                M.permute(x, y, x0, y0, inverse=True)
+                finals[prec] = (x0.double().cpu().numpy(), y0.double().cpu().numpy())
+            del x, y
+    extras = dict(host_seconds=dict(generate=t_gen, **{f"reorder_{k}": v for k, v in reorder_s.items()}))
+    cpu = None
+    if not args.no_cpu_baseline and "f32" in finals:
+        cpu, top = cpu_baseline(m, SWEEPS, budget_s=0.0)
+        from oracle import smooth as osm
+        ex, ey = osm.jacobi(top, m.x, m.y, SWEEPS, threads=cpu["cores"])
+        ext = float(np.ptp(m.xy, axis=0).max())
+        d32 = np.hypot(finals["f32"][0] - ex, finals["f32"][1] - ey) / ext
+        d64 = np.maximum(np.abs(finals["f64"][0] - ex), np.abs(finals["f64"][1] - ey)) / ext
+        extras["fp32_error_vs_fp64_oracle"] = dict(max=float(d32.max()), rms=float(np.sqrt(np.mean(d32 ** 2))),
+                                                   sweeps=SWEEPS, normalised_by="mesh extent")
+        extras["fp64_max_error_vs_oracle"] = float(d64.max())
+        log(f"FP32 error vs FP64 oracle after {SWEEPS} sweeps: max {d32.max():.3e}, rms "
+            f"{np.sqrt(np.mean(d32 ** 2)):.3e} of extent; FP64 max {d64.max():.3e}")
+    h = results.get("rdr_f32") or next(iter(results.values()))
+    return result_line(
+        h["vertex_updates_per_s"], args.steps, args.warmup, h["ms_per_step"], "f32",
+        {"workload": f"graded mesh refined 4x toward a seeded curve: {SWEEPS} Jacobi sweeps per step, "
+                     "RDR ordering, float32 storage and accumulation",
+         "n": info["n"], "n_free": info["n_free"], "n_tri": m.T, "nnz": info["nnz"], "sweeps_per_step": SWEEPS},
+        roofline_of(h), cpu, per_ordering=strip(results), extras=extras)
+
+
+def bench_batch512(torch, args):
+    import meshgen
+    from paper_1606_00803_amd import lms
+    SWEEPS = 30
+    t0 = time.perf_counter()
+    ms = meshgen.batch()
+    u, v_off, t_off = meshgen.concat(ms)
+    local = np.concatenate([mm.tri for mm in ms])
+    B = lms.Mesh.build_csr_batched(v_off, t_off, local)
+    info = B.info()
+    log(f"batch: {len(ms)} meshes, n={info['n']} T={u.T} nnz={info['nnz']} ({time.perf_counter() - t0:.1f}s)")
+    results = {}
+    for kind in ("ori", "rdr"):
+        B.reorder(kind, seed=RANDOM_SEED, x0=u.x, y0=u.y)
+        for prec in ("f64", "f32"):
+            r, _ = run_fixed(torch, B, u, kind, prec, SWEEPS, args.steps, args.warmup)
+            results[f"{kind}_{prec}"] = r
+            log(f"{kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  sweep "
+                f"{r['sweep_us_events']:8.2f} us  {r['achieved_gbs']:8.1f} GB/s  [{r['sweep_kernel']}]")
+    h = results["rdr_f64"]
+    return result_line(
+        h["vertex_updates_per_s"], args.steps, args.warmup, h["ms_per_step"], "f64",
+        {"workload": f"batch of {len(ms)} jittered grids, sizes log-uniform 1k-200k vertices, "
+                     f"{SWEEPS} sweeps each in one launch per sweep, RDR per mesh, float64",
+         "n": info["n"], "n_mesh": len(ms), "sweeps_per_step": SWEEPS},
+        roofline_of(h), None, per_ordering=strip(results))
+
+
+def bench_graded64m(torch, args):
+    import meshgen
+    from paper_1606_00803_amd import lms
+    t0 = time.perf_counter()
+    m = meshgen.graded64m()
+    t_gen = time.perf_counter() - t0
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    info = M.info()
+    log(f"graded64m n={info['n']} n_free={info['n_free']} T={m.T} colours={info['n_colors']} gen={t_gen:.1f}s")
+    runs = {}
+    for kind in ("rdr", "random"):
+        M.reorder(kind, seed=RANDOM_SEED + 3, x0=m.x, y0=m.y)
+        x0 = torch.as_tensor(m.x, dtype=torch.float32, device="cuda")
+        y0 = torch.as_tensor(m.y, dtype=torch.float32, device="cuda")
+        x = torch.empty_like(x0)
+        y = torch.empty_like(y0)
+        for scheme in ("jacobi", "multicolor"):
+            M.permute(x0, y0, x, y)
+            M.smooth(x, y, scheme=scheme, max_iters=2, check_quality=False)   # tune
+            M.permute(x0, y0, x, y)
+            with Timer(torch) as t:
+                r = M.smooth(x, y, scheme=scheme, max_iters=2000, tol=5e-6)
+            runs[f"{kind}_{scheme}"] = dict(iters=r["iters"], stopped_by=r["stopped_by"], q0=r["q0"],
+                                            q_final=r["q_final"], seconds_to_criterion=t.wall,
+                                            vertex_updates_per_s_incl_quality=info["n_free"] * r["iters"] / t.wall)
+            log(kind, scheme, runs[f"{kind}_{scheme}"])
+        del x, y, x0, y0
+    h = runs["rdr_jacobi"]
+    return result_line(
+        h["vertex_updates_per_s_incl_quality"], 1, 1, h["seconds_to_criterion"] * 1e3, "f32",
+        {"workload": "graded ocean-like mesh ~64M vertices with holes and two refinement bands, "
+                     "smoothed to dQ < 5e-6, float32 coordinates, float64 quality",
+         "n": info["n"], "n_free": info["n_free"]},
+        None, None, runs=runs, host_seconds=dict(generate=t_gen))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ocean", choices=["ocean", "graded16m", "batch512", "graded64m"])
     ap.add_argument("--orderings", default=",".join(ORDER_NAMES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="only the headline timing")
-    ap.add_argument("--nx", type=int, default=1000)
+    ap.add_argument("--no-extras", action="store_true", help="only the per-ordering timings")
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a known-size kernel for counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described but not built.", file=sys.stderr)
         sys.exit(2)
-
     import torch
-    import meshgen
     from paper_1606_00803_amd import lms
     if not os.path.exists(lms.LIB_PATH):
         from paper_1606_00803_amd import build
         build.build()
     lms.load()
     assert torch.cuda.is_available(), "no GPU visible"
-    dev = torch.device("cuda")
-
-    t0 = time.perf_counter()
-    m = meshgen.ocean(nx=args.nx)
-    t_gen = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    M = lms.Mesh.build_csr(m.n, m.tri)
-    t_csr = time.perf_counter() - t0
-    info = M.info()
-    n, n_free, nnz = info["n"], info["n_free"], info["nnz"]
-    log(f"mesh n={n} n_free={n_free} T={m.T} nnz={nnz} colours={info['n_colors']} "
-        f"gen={t_gen:.2f}s csr={t_csr:.2f}s")
-
-    orderings = [o for o in args.orderings.split(",") if o]
-    results = {}
-    reorder_s = {}
-    headline = None
-    for kind in orderings:
-        t0 = time.perf_counter()
-        M.reorder(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)
-        reorder_s[kind] = time.perf_counter() - t0
-        for prec, dt, s in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
-            x0 = torch.as_tensor(m.x, dtype=dt, device=dev)
-            y0 = torch.as_tensor(m.y, dtype=dt, device=dev)
-            x = torch.empty_like(x0)
-            y = torch.empty_like(y0)
-            M.permute(x0, y0, x, y)
-            tx = torch.empty_like(x)
-            ty = torch.empty_like(y)
-            for _ in range(args.warmup):
-                M.smooth(x, y, tx, ty, max_iters=SWEEPS, check_quality=False)
-            stream = torch.cuda.current_stream()
-            ev0 = torch.cuda.Event(enable_timing=True)
-            ev1 = torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            w0 = time.perf_counter()
-            ev0.record(stream)
-            for _ in range(args.steps):
-                M.smooth(x, y, tx, ty, max_iters=SWEEPS, check_quality=False)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - w0
-            ev_ms = ev0.elapsed_time(ev1)
-            launches = args.steps * SWEEPS
-            sweep_us = ev_ms * 1e3 / launches
-            b = sweep_bytes(n, n_free, nnz, s)
-            results[f"{kind}_{prec}"] = dict(
-                sweep_kernel=M.sweep_config(prec).split(" ")[0],
-                vertex_updates_per_s=n_free * launches / wall,
-                ms_per_step=wall * 1e3 / args.steps,
-                sweep_us_events=sweep_us,
-                achieved_gbs=b / (sweep_us * 1e-6) / 1e9,
-                frac_hbm=b / (sweep_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                bytes_per_sweep=b)
-            log(f"{kind:7s} {prec}: {results[f'{kind}_{prec}']['vertex_updates_per_s']/1e9:7.2f} G upd/s  "
-                f"sweep {sweep_us:7.2f} us  {results[f'{kind}_{prec}']['achieved_gbs']:8.1f} GB/s")
-            if kind == "rdr" and prec == "f64":
-                headline = dict(wall=wall, ev_ms=ev_ms, sweep_us=sweep_us, bytes=b,
-                                kernel=M.sweep_config("f64"))
-                log("sweep variants (RDR, f64):", headline["kernel"])
-            del x0, y0, x, y, tx, ty
-
-    extras = {}
-    if not args.no_extras:
-        # multicolour in-place sweeps and the quality pass, RDR ordering, float64
-        M.reorder("rdr", x0=m.x, y0=m.y)
-        x0 = torch.as_tensor(m.x, dtype=torch.float64, device=dev)
-        y0 = torch.as_tensor(m.y, dtype=torch.float64, device=dev)
-        x = torch.empty_like(x0)
-        y = torch.empty_like(y0)
-        M.permute(x0, y0, x, y)
-        M.smooth(x, y, scheme="multicolor", max_iters=SWEEPS, check_quality=False)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        for _ in range(args.steps):
-            M.smooth(x, y, scheme="multicolor", max_iters=SWEEPS, check_quality=False)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        extras["multicolor_rdr_f64_vertex_updates_per_s"] = n_free * SWEEPS * args.steps / wall
-        M.quality(x, y)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        for _ in range(args.steps):
-            M.quality(x, y)
-        wall = time.perf_counter() - w0
-        extras["quality_pass_us"] = wall * 1e6 / args.steps
-        # Algorithm 1 to the paper's criterion (dQ < 5e-6), RDR, float64
-        M.permute(x0, y0, x, y)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        r = M.smooth(x, y, max_iters=2000, tol=5e-6)
-        extras["to_criterion"] = dict(iters=r["iters"], stopped_by=r["stopped_by"],
-                                      q0=r["q0"], q_final=r["q_final"],
-                                      seconds=time.perf_counter() - w0)
-        extras["host_seconds"] = dict(generate=t_gen, build_csr=t_csr, **{f"reorder_{k}": v for k, v in reorder_s.items()})
-        del x0, y0, x, y
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import mesh as omesh
-        from oracle import smooth as osm
-        top = omesh.topology(m.n, m.tri)
-        try:
-            cores = len(os.sched_getaffinity(0))
-        except AttributeError:
-            cores = os.cpu_count() or 1
-        cores = max(1, min(cores, 16))
-        reps = 0
-        w0 = time.perf_counter()
-        while reps < 3 or time.perf_counter() - w0 < 3.0:
-            osm.jacobi(top, m.x, m.y, SWEEPS, threads=cores)
-            reps += 1
-        wall = time.perf_counter() - w0
-        cpu = dict(value=n_free * SWEEPS * reps / wall, unit="vertex-updates/s", cores=cores,
-                   kind="oracle",
-                   sample=f"the full workload (ocean mesh, {SWEEPS} float64 Jacobi sweeps, ORI labels) "
-                          f"repeated {reps} times, OpenMP static schedule")
-        log(f"oracle on {cores} host threads: {cpu['value']/1e9:.3f} G upd/s")
-
-    h = headline or next(iter([dict(wall=float('nan'), ev_ms=float('nan'), sweep_us=float('nan'), bytes=0)]))
-    value = n_free * SWEEPS * args.steps / h["wall"]
-    achieved = h["bytes"] / (h["sweep_us"] * 1e-6) / 1e9
-    out = {
-        "metric": "vertex-updates/sec and % HBM roofline per ordering (ORI/BFS/RDR/random), FP64 vs FP32",
-        "value": value,
-        "unit": "vertex-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": h["wall"] * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"ocean-like mesh: {args.nx}x{args.nx} jittered grid, ~30% disc-union holes, "
-                               f"{SWEEPS} Jacobi sweeps per step, RDR ordering, float64",
-                   "n": n, "n_free": n_free, "n_tri": m.T, "nnz": nnz, "sweeps_per_step": SWEEPS},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": h.get("kernel", ""), "bytes_per_launch": h["bytes"],
-                     "avg_launch_us": h["sweep_us"]},
-        "cpu_baseline": cpu,
-        "per_ordering": results,
-        "extras": extras,
-    }
+    fn = dict(ocean=bench_ocean, graded16m=bench_graded16m, batch512=bench_batch512,
+              graded64m=bench_graded64m)[args.workload]
+    out = fn(torch, args)
     print(json.dumps(out), flush=True)
 
 

@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "Mesh", "jittered_grid", "ocean", "batch", "concat", "regular_grid",
-    "wheel", "mesh_hash", "graded",
+    "wheel", "mesh_hash", "graded", "graded16m", "graded64m",
 ]
 
 
@@ -272,6 +272,19 @@ def wheel(k: int, radius: float = 1.0, centre=(0.3, -0.2), seed: int | None = No
     return Mesh(xy, tri, dict(kind="wheel", k=k, n=k + 1, T=k))
 
 
-def graded(*args, **kwargs) -> Mesh:  # pragma: no cover - implemented in meshgen.graded
+def graded(n0: int, seed: int = 3, curves: int = 1, band_w: float = 0.04,
+           land_fraction: float = 0.0, jitter: float = 0.3) -> Mesh:
+    """Graded mesh refined by triangle bisection toward seeded curves (see
+    :mod:`meshgen.graded_mesh`)."""
     from .graded_mesh import graded as _g
-    return _g(*args, **kwargs)
+    return _g(n0, seed=seed, curves=curves, band_w=band_w, land_fraction=land_fraction, jitter=jitter)
+
+
+def graded16m() -> Mesh:
+    """~16M vertices: one refinement band (edge/4 within 0.04, edge/2 within 0.08)."""
+    return graded(2416, seed=3)
+
+
+def graded64m() -> Mesh:
+    """~64M vertices: two refinement bands and ~30% disc-union holes."""
+    return graded(4736, seed=5, curves=2, land_fraction=0.3)

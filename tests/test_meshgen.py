@@ -41,3 +41,24 @@ def test_batch_and_concat():
     assert t_off[-1] == u.T
     for i, m in enumerate(ms):
         assert np.array_equal(u.tri[t_off[i]:t_off[i + 1]] - v_off[i], m.tri)
+
+
+def test_graded_mesh_is_valid_and_refined():
+    m = meshgen.graded(129, seed=3)
+    top = omesh.topology(m.n, m.tri)
+    assert m.n > 2.0 * 129 * 129                 # the band was refined
+    d = top.degree[top.fixed == 0]
+    assert d.min() >= 3 and d.max() <= 12
+    p = m.xy[m.tri]
+    cross = ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+             - (p[:, 1, 1] - p[:, 0, 1]) * (p[:, 2, 0] - p[:, 0, 0]))
+    assert (cross > 0).mean() > 0.999             # counter-clockwise (jitter may flip a sliver)
+    a = meshgen.graded(129, seed=3)
+    assert meshgen.mesh_hash(a) == meshgen.mesh_hash(m)
+
+
+def test_graded_mesh_with_holes():
+    m = meshgen.graded(97, seed=5, curves=2, land_fraction=0.3)
+    top = omesh.topology(m.n, m.tri)
+    assert m.meta["discs"] > 0
+    assert int((top.fixed == 0).sum()) == m.meta["n_free"]
