@@ -63,21 +63,20 @@ def device_source_hash():
 
 
 def counters_traffic(kernel_name):
-    """HBM traffic per launch from the committed counter summary, when it was
-    taken on the current kernel source and the same sweep variant."""
+    """HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the
+    committed counter summary, when it was taken on the current kernel source;
+    the summary lists every sweep variant the autotuner timed."""
     try:
         text = open(COUNTERS_MD).read()
     except OSError:
         return None
-    fields = dict(re.findall(r"^- (\w+): (\S+)$", text, flags=re.M))
-    if fields.get("source_sha256") != device_source_hash():
+    src = re.search(r"^- source_sha256: (\S+)$", text, flags=re.M)
+    if not src or src.group(1) != device_source_hash():
         return None
-    if fields.get("variant") != kernel_name:
-        return None
-    try:
-        return float(fields["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    for name, traffic in re.findall(r"^\| `(\S+)` \|[^|]*\|[^|]*\| (\d+) \|", text, flags=re.M):
+        if name == kernel_name:
+            return float(traffic)
+    return None
 
 
 class Timer:
@@ -204,8 +203,11 @@ def bench_ocean(torch, args):
     log(f"ocean mesh n={info['n']} n_free={info['n_free']} T={m.T} nnz={info['nnz']} "
         f"colours={info['n_colors']} gen={t_gen:.2f}s csr={t_csr:.2f}s")
     if args.calibration_copy_mb:
-        # a copy of known size, for scaling the memory counters
+        # a device copy of known size, for scaling the memory counters; a 1 GiB
+        # fill in between evicts the source from the caches first
         a = torch.empty(args.calibration_copy_mb << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+        flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(0.0)
+        del flush
         torch.empty_like(a).copy_(a)
         torch.cuda.synchronize()
         del a

@@ -51,6 +51,27 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// Tile walked by workgroup b of nb.  MAP = 0: tile b (consecutive tiles land
+// on different XCDs, so all XCDs sweep one narrow window of the ids);
+// MAP < 0: xcd_tile (each XCD one contiguous eighth); MAP = k > 0: each XCD
+// takes runs of k consecutive tiles (neighbouring tiles share an L2, and the
+// XCDs still advance together through the ids).  The tail that does not fill
+// a whole round of 8 runs keeps tile = b.  Every mapping is a bijection.
+template <int MAP>
+__device__ __forceinline__ int tile_of(int b, int nb) {
+    if constexpr (MAP == 0) {
+        return b;
+    } else if constexpr (MAP < 0) {
+        return xcd_tile(b, nb);
+    } else {
+        constexpr int span = kXcds * MAP;
+        const int full = (nb / span) * span;
+        if (b >= full) return b;
+        const int xcd = b % kXcds, local = b / kXcds;
+        return ((local / MAP) * kXcds + xcd) * MAP + local % MAP;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Jacobi sweep, Eq. 1 for every free vertex: dst[v] = (sum of src[u] over the
 // neighbours u of v, in ascending label) / deg(v).  Fixed rows are empty and
@@ -63,7 +84,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // per pass); finally each thread sums its own row out of LDS in order and
 // divides.  A slice with more than CAP entries takes several passes; the
 // partial sums carry over, so the summation order stays the row's order.
-template <typename T, int BS, int CAP, bool SWZ>
+template <typename T, int BS, int CAP, int MAP>
 __global__ __launch_bounds__(BS) void k_jacobi(const int32_t *__restrict__ row_ptr,
                                                const int32_t *__restrict__ col,
                                                const T *__restrict__ sx, const T *__restrict__ sy,
@@ -77,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_jacobi(const int32_t *__restrict__ row_p
     if (st && st->done) return;
 
     const int nb = int(gridDim.x);
-    const int tile = SWZ ? xcd_tile(int(blockIdx.x), nb) : int(blockIdx.x);
+    const int tile = tile_of<MAP>(int(blockIdx.x), nb);
     const int32_t r0 = tile * BS;
     const int tid = int(threadIdx.x);
     const int rows = min(BS, n - r0);
@@ -132,7 +153,7 @@ __device__ __forceinline__ int32_t load_index(const int32_t *p) {
 // independent, so they are in flight together), and adds each row in order.
 // No LDS and no barriers.  Sums in the same order as k_jacobi: same bits.
 // NT: neighbour indices are loaded with the non-temporal hint.
-template <typename T, int BS, int U, int R, bool SWZ, bool NT>
+template <typename T, int BS, int U, int R, int MAP, bool NT>
 __global__ __launch_bounds__(BS) void k_jacobi_row(const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col,
                                                    const T *__restrict__ sx, const T *__restrict__ sy,
@@ -140,7 +161,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_row(const int32_t *__restrict__ r
                                                    const StopState *__restrict__ st) {
     if (st && st->done) return;
     const int nb = int(gridDim.x);
-    const int tile = SWZ ? xcd_tile(int(blockIdx.x), nb) : int(blockIdx.x);
+    const int tile = tile_of<MAP>(int(blockIdx.x), nb);
     const int32_t v0 = tile * (BS * R) + int32_t(threadIdx.x);
     int32_t b[R], e[R];
 #pragma unroll
@@ -202,14 +223,14 @@ __global__ __launch_bounds__(BS) void k_jacobi_row(const int32_t *__restrict__ r
 // its neighbours without first reading row offsets, and every index load of
 // a wavefront is one coalesced line.  Rows have at most W entries.  Each
 // thread owns R rows BS apart.  Entries are in the CSR order: same bits.
-template <typename T, int BS, int W, int R, bool SWZ>
+template <typename T, int BS, int W, int R, int MAP>
 __global__ __launch_bounds__(BS) void k_jacobi_ell(const int32_t *__restrict__ ell,
                                                    const T *__restrict__ sx, const T *__restrict__ sy,
                                                    T *__restrict__ dx, T *__restrict__ dy, int32_t n,
                                                    const StopState *__restrict__ st) {
     if (st && st->done) return;
     const int nb = int(gridDim.x);
-    const int tile = SWZ ? xcd_tile(int(blockIdx.x), nb) : int(blockIdx.x);
+    const int tile = tile_of<MAP>(int(blockIdx.x), nb);
     const int32_t v0 = tile * (BS * R) + int32_t(threadIdx.x);
     int32_t u[R][W];
 #pragma unroll
@@ -284,14 +305,14 @@ __global__ __launch_bounds__(256) void k_unpack(const vec2_t<T> *__restrict__ a,
 }
 
 // k_jacobi_ell on the interleaved copy: same order of additions, same bits.
-template <typename T, int BS, int W, int R, bool SWZ>
+template <typename T, int BS, int W, int R, int MAP>
 __global__ __launch_bounds__(BS) void k_jacobi_ell2(const int32_t *__restrict__ ell,
                                                     const vec2_t<T> *__restrict__ src,
                                                     vec2_t<T> *__restrict__ dst, int32_t n,
                                                     const StopState *__restrict__ st) {
     if (st && st->done) return;
     const int nb = int(gridDim.x);
-    const int tile = SWZ ? xcd_tile(int(blockIdx.x), nb) : int(blockIdx.x);
+    const int tile = tile_of<MAP>(int(blockIdx.x), nb);
     const int32_t v0 = tile * (BS * R) + int32_t(threadIdx.x);
     int32_t u[R][W];
 #pragma unroll
@@ -326,6 +347,66 @@ __global__ __launch_bounds__(BS) void k_jacobi_ell2(const int32_t *__restrict__ 
             }
         if (cnt == 0) continue;
         const T c = T(cnt);
+        vec2_t<T> o;
+        o.x = ax / c;
+        o.y = ay / c;
+        dst[v0 + r * BS] = o;
+    }
+}
+
+// k_jacobi_row on the interleaved copy: row offsets and the unpadded index
+// stream (4 bytes per entry fewer than the padded copy's empty slots), one
+// load per neighbour.  Same order of additions, same bits.
+template <typename T, int BS, int U, int R, int MAP>
+__global__ __launch_bounds__(BS) void k_jacobi_row2(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const vec2_t<T> *__restrict__ src,
+                                                    vec2_t<T> *__restrict__ dst, int32_t n,
+                                                    const StopState *__restrict__ st) {
+    if (st && st->done) return;
+    const int nb = int(gridDim.x);
+    const int tile = tile_of<MAP>(int(blockIdx.x), nb);
+    const int32_t v0 = tile * (BS * R) + int32_t(threadIdx.x);
+    int32_t b[R], e[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t v = v0 + r * BS;
+        b[r] = v < n ? row_ptr[v] : 0;
+        e[r] = v < n ? row_ptr[v + 1] : 0;
+    }
+    int32_t u[R][U];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < U; ++k) u[r][k] = b[r] + k < e[r] ? __builtin_nontemporal_load(col + b[r] + k) : -1;
+    vec2_t<T> p[R][U];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (u[r][k] >= 0) {
+                p[r][k] = src[u[r][k]];
+            } else {
+                p[r][k].x = T(0);
+                p[r][k].y = T(0);
+            }
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (e[r] == b[r]) continue;
+        T ax = T(0), ay = T(0);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (u[r][k] >= 0) {
+                ax += p[r][k].x;
+                ay += p[r][k].y;
+            }
+        for (int32_t j = b[r] + U; j < e[r]; ++j) {  // rows longer than U, in order
+            const vec2_t<T> q = src[col[j]];
+            ax += q.x;
+            ay += q.y;
+        }
+        const T c = T(e[r] - b[r]);
         vec2_t<T> o;
         o.x = ax / c;
         o.y = ay / c;
@@ -612,7 +693,7 @@ struct DeviceState {
     int smooth_cfg[2] = {-1, -1};    // variant lms_smooth uses (may sweep the interleaved copy)
     void *pk[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [precision][ping|pong] interleaved copies
     size_t pk_n[2] = {0, 0};
-    float tune_us[2][32] = {};       // measured time per variant (microseconds per sweep)
+    float tune_us[2][64] = {};       // measured time per variant (microseconds per sweep)
 };
 
 namespace {
@@ -709,88 +790,115 @@ void launch_check() {
 
 // The sweep kernel variants the autotuner chooses from.  All of them sum each
 // row in ascending neighbour order from 0, so they return identical bits.
-//   ROW(id, BS, U, R, SWZ, NT)   k_jacobi_row
-//   LDS(id, BS, CAP, SWZ)        k_jacobi
-//   ELL(id, BS, W, R, SWZ)       k_jacobi_ell (eligible when the padded width is W)
-//   ELL2(id, BS, W, R, SWZ)      k_jacobi_ell2 on the interleaved copy (lms_smooth only)
-#define LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2) \
-    ROW(0, 256, 8, 1, true, true)        \
-    ROW(1, 256, 8, 1, false, true)       \
-    ROW(2, 64, 8, 1, true, true)         \
-    ROW(3, 256, 8, 1, true, false)       \
-    ROW(4, 256, 8, 2, true, true)        \
-    ROW(5, 128, 8, 2, true, false)       \
-    ROW(6, 256, 4, 2, true, false)       \
-    LDS(7, 256, 2048, true)              \
-    LDS(8, 128, 1024, true)              \
-    LDS(9, 64, 512, true)                \
-    ELL(10, 256, 8, 1, true)             \
-    ELL(11, 256, 8, 2, true)             \
-    ELL(12, 128, 8, 2, false)            \
-    ELL(13, 64, 8, 1, true)              \
-    ELL(14, 256, 8, 4, true)             \
-    ELL(15, 256, 12, 1, true)            \
-    ELL(16, 256, 12, 2, true)            \
-    ELL(17, 256, 16, 1, true)            \
-    ELL2(18, 256, 8, 1, true)            \
-    ELL2(19, 128, 8, 2, false)           \
-    ELL2(20, 64, 8, 1, true)             \
-    ELL2(21, 256, 8, 2, true)            \
-    ELL2(22, 128, 8, 1, false)           \
-    ELL2(23, 256, 12, 1, true)           \
-    ELL2(24, 256, 16, 1, true)
-constexpr int kNumSweepConfigs = 25;
+// MAP is the tile order (see tile_of: 0 linear, -1 one range per XCD, k runs
+// of k tiles per XCD).
+//   ROW(id, BS, U, R, MAP, NT)   k_jacobi_row
+//   LDS(id, BS, CAP, MAP)        k_jacobi
+//   ELL(id, BS, W, R, MAP)       k_jacobi_ell (eligible when the padded width is W)
+//   ELL2(id, BS, W, R, MAP)      k_jacobi_ell2 on the interleaved copy (lms_smooth only)
+//   ROW2(id, BS, U, R, MAP)      k_jacobi_row2 on the interleaved copy (lms_smooth only)
+#define LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2) \
+    ROW(0, 256, 8, 1, -1, true)                  \
+    ROW(1, 256, 8, 1, 0, true)                   \
+    ROW(2, 64, 8, 1, -1, true)                   \
+    ROW(3, 256, 8, 1, -1, false)                 \
+    ROW(4, 256, 8, 2, -1, true)                  \
+    ROW(5, 128, 8, 2, -1, false)                 \
+    ROW(6, 256, 8, 1, 16, false)                 \
+    LDS(7, 256, 2048, -1)                        \
+    LDS(8, 128, 1024, -1)                        \
+    LDS(9, 64, 512, -1)                          \
+    ELL(10, 256, 8, 1, -1)                       \
+    ELL(11, 256, 8, 2, -1)                       \
+    ELL(12, 128, 8, 2, 0)                        \
+    ELL(13, 64, 8, 1, -1)                        \
+    ELL(14, 256, 8, 4, -1)                       \
+    ELL(15, 256, 12, 1, -1)                      \
+    ELL(16, 256, 12, 2, -1)                      \
+    ELL(17, 256, 16, 1, -1)                      \
+    ELL2(18, 256, 8, 1, -1)                      \
+    ELL2(19, 128, 8, 2, 0)                       \
+    ELL2(20, 64, 8, 1, -1)                       \
+    ELL2(21, 256, 8, 2, -1)                      \
+    ELL2(22, 128, 8, 1, 0)                       \
+    ELL2(23, 256, 12, 1, -1)                     \
+    ELL2(24, 256, 16, 1, -1)                     \
+    ELL2(25, 128, 8, 1, 16)                      \
+    ELL2(26, 128, 8, 2, 16)                      \
+    ELL2(27, 256, 8, 1, 4)                       \
+    ELL2(28, 128, 8, 1, 64)                      \
+    ELL2(29, 256, 12, 1, 0)                      \
+    ELL2(30, 256, 16, 1, 0)                      \
+    ROW2(31, 256, 8, 1, 0)                       \
+    ROW2(32, 128, 8, 2, 0)                       \
+    ROW2(33, 256, 8, 1, -1)                      \
+    ROW2(34, 128, 8, 1, 16)                      \
+    ROW2(35, 64, 8, 1, 0)
+constexpr int kNumSweepConfigs = 36;
 constexpr int kDefaultSweepConfig = 0;
+
+std::string map_name(int map) {
+    return map == 0 ? "linear" : (map < 0 ? "xcd" : "xcd" + std::to_string(map));
+}
 
 std::string sweep_config_name(int cfg) {
     char buf[96];
     switch (cfg) {
-#define ROW(id, bs, u, r, swz, nt)                                                                  \
-    case id:                                                                                        \
-        std::snprintf(buf, sizeof(buf), "row/bs%d/u%d/r%d/%s%s", bs, u, r, swz ? "xcd" : "linear", \
-                      nt ? "/nt" : "");                                                             \
+#define ROW(id, bs, u, r, map, nt)                                                              \
+    case id:                                                                                    \
+        std::snprintf(buf, sizeof(buf), "row/bs%d/u%d/r%d/%s%s", bs, u, r, map_name(map).c_str(), \
+                      nt ? "/nt" : "");                                                         \
         return buf;
-#define LDS(id, bs, cap, swz)                                                                      \
-    case id:                                                                                       \
-        std::snprintf(buf, sizeof(buf), "lds/bs%d/cap%d/%s", bs, cap, swz ? "xcd" : "linear");    \
+#define LDS(id, bs, cap, map)                                                                    \
+    case id:                                                                                     \
+        std::snprintf(buf, sizeof(buf), "lds/bs%d/cap%d/%s", bs, cap, map_name(map).c_str());    \
         return buf;
-#define ELL(id, bs, w, r, swz)                                                                     \
-    case id:                                                                                       \
-        std::snprintf(buf, sizeof(buf), "ell/bs%d/w%d/r%d/%s", bs, w, r, swz ? "xcd" : "linear"); \
+#define ELL(id, bs, w, r, map)                                                                   \
+    case id:                                                                                     \
+        std::snprintf(buf, sizeof(buf), "ell/bs%d/w%d/r%d/%s", bs, w, r, map_name(map).c_str()); \
         return buf;
-#define ELL2(id, bs, w, r, swz)                                                                     \
-    case id:                                                                                        \
-        std::snprintf(buf, sizeof(buf), "ell2/bs%d/w%d/r%d/%s", bs, w, r, swz ? "xcd" : "linear"); \
+#define ELL2(id, bs, w, r, map)                                                                   \
+    case id:                                                                                      \
+        std::snprintf(buf, sizeof(buf), "ell2/bs%d/w%d/r%d/%s", bs, w, r, map_name(map).c_str()); \
         return buf;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2)
+#define ROW2(id, bs, u, r, map)                                                                   \
+    case id:                                                                                      \
+        std::snprintf(buf, sizeof(buf), "row2/bs%d/u%d/r%d/%s", bs, u, r, map_name(map).c_str()); \
+        return buf;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
+#undef ROW2
     }
     return "unknown";
 }
 
-// Padded width an ELL variant needs (0: not an ELL variant).
+// Padded width an ELL variant needs (0: not a padded-index variant).
 int sweep_config_ell_width(int cfg) {
     switch (cfg) {
-#define ROW(id, bs, u, r, swz, nt) \
+#define ROW(id, bs, u, r, map, nt) \
     case id:                       \
         return 0;
-#define LDS(id, bs, cap, swz) \
+#define LDS(id, bs, cap, map) \
     case id:                  \
         return 0;
-#define ELL(id, bs, w, r, swz) \
+#define ELL(id, bs, w, r, map) \
     case id:                   \
         return w;
-#define ELL2(id, bs, w, r, swz) \
+#define ELL2(id, bs, w, r, map) \
     case id:                    \
         return w;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2)
+#define ROW2(id, bs, u, r, map) \
+    case id:                    \
+        return 0;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
+#undef ROW2
     }
     return -1;
 }
@@ -798,23 +906,27 @@ int sweep_config_ell_width(int cfg) {
 // Variants that sweep the interleaved (x, y) working copy.
 bool sweep_config_packed(int cfg) {
     switch (cfg) {
-#define ROW(id, bs, u, r, swz, nt) \
+#define ROW(id, bs, u, r, map, nt) \
     case id:                       \
         return false;
-#define LDS(id, bs, cap, swz) \
+#define LDS(id, bs, cap, map) \
     case id:                  \
         return false;
-#define ELL(id, bs, w, r, swz) \
+#define ELL(id, bs, w, r, map) \
     case id:                   \
         return false;
-#define ELL2(id, bs, w, r, swz) \
+#define ELL2(id, bs, w, r, map) \
     case id:                    \
         return true;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2)
+#define ROW2(id, bs, u, r, map) \
+    case id:                    \
+        return true;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
+#undef ROW2
     }
     return false;
 }
@@ -824,37 +936,37 @@ bool sweep_config_eligible(int cfg, const Mesh &M) {
     return w == 0 || (w > 0 && w == M.ell_w);
 }
 
+int grid_for(int64_t n, int rows_per_block) { return int((n + rows_per_block - 1) / rows_per_block); }
+
 template <typename T>
 void launch_sweep_cfg(int cfg, const DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
                       const StopState *st, hipStream_t s) {
     const int64_t n = M.n;
     switch (cfg) {
-#define ROW(id, bs, u, r, swz, nt)                                                                   \
-    case id:                                                                                         \
-        k_jacobi_row<T, bs, u, r, swz, nt><<<int((n + bs * r - 1) / (bs * r)), bs, 0, s>>>(          \
-            d.row_ptr, d.col, sx, sy, dx, dy, M.n, st);                                              \
+#define ROW(id, bs, u, r, map, nt)                                                                         \
+    case id:                                                                                               \
+        k_jacobi_row<T, bs, u, r, map, nt><<<grid_for(n, bs * r), bs, 0, s>>>(d.row_ptr, d.col, sx, sy, dx, \
+                                                                              dy, M.n, st);                 \
         break;
-#define LDS(id, bs, cap, swz)                                                                         \
-    case id:                                                                                          \
-        k_jacobi<T, bs, cap, swz><<<int((n + bs - 1) / bs), bs, 0, s>>>(d.row_ptr, d.col, sx, sy, dx, \
-                                                                          dy, M.n, st);              \
+#define LDS(id, bs, cap, map)                                                                                 \
+    case id:                                                                                                  \
+        k_jacobi<T, bs, cap, map><<<grid_for(n, bs), bs, 0, s>>>(d.row_ptr, d.col, sx, sy, dx, dy, M.n, st);   \
         break;
-#define ELL(id, bs, w, r, swz)                                                                       \
+#define ELL(id, bs, w, r, map)                                                                       \
     case id:                                                                                         \
         if (M.ell_w != w) fail(LMS_ERR_STATE, "padded adjacency width does not match the variant"); \
-        k_jacobi_ell<T, bs, w, r, swz><<<int((n + bs * r - 1) / (bs * r)), bs, 0, s>>>(               \
-            d.ell, sx, sy, dx, dy, M.n, st);                                                         \
+        k_jacobi_ell<T, bs, w, r, map><<<grid_for(n, bs * r), bs, 0, s>>>(d.ell, sx, sy, dx, dy, M.n, st); \
         break;
-#define ELL2(id, bs, w, r, swz) \
-    case id:                    \
-        fail(LMS_ERR_STATE, "interleaved variant launched on separate x, y arrays");
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2)
+#define ELL2(id, bs, w, r, map)
+#define ROW2(id, bs, u, r, map)
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
+#undef ROW2
         default:
-            fail(LMS_ERR_STATE, "bad sweep configuration");
+            fail(LMS_ERR_STATE, "interleaved or unknown variant launched on separate x, y arrays");
     }
 }
 
@@ -863,20 +975,25 @@ void launch_sweep2_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_
                        const StopState *st, hipStream_t s) {
     const int64_t n = M.n;
     switch (cfg) {
-#define ROW(id, bs, u, r, swz, nt)
-#define LDS(id, bs, cap, swz)
-#define ELL(id, bs, w, r, swz)
-#define ELL2(id, bs, w, r, swz)                                                                       \
-    case id:                                                                                          \
-        if (M.ell_w != w) fail(LMS_ERR_STATE, "padded adjacency width does not match the variant");  \
-        k_jacobi_ell2<T, bs, w, r, swz><<<int((n + bs * r - 1) / (bs * r)), bs, 0, s>>>(d.ell, src, dst, \
-                                                                                         M.n, st);    \
+#define ROW(id, bs, u, r, map, nt)
+#define LDS(id, bs, cap, map)
+#define ELL(id, bs, w, r, map)
+#define ELL2(id, bs, w, r, map)                                                                         \
+    case id:                                                                                            \
+        if (M.ell_w != w) fail(LMS_ERR_STATE, "padded adjacency width does not match the variant");    \
+        k_jacobi_ell2<T, bs, w, r, map><<<grid_for(n, bs * r), bs, 0, s>>>(d.ell, src, dst, M.n, st);   \
         break;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2)
+#define ROW2(id, bs, u, r, map)                                                                           \
+    case id:                                                                                              \
+        k_jacobi_row2<T, bs, u, r, map><<<grid_for(n, bs * r), bs, 0, s>>>(d.row_ptr, d.col, src, dst,    \
+                                                                           M.n, st);                      \
+        break;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
+#undef ROW2
         default:
             fail(LMS_ERR_STATE, "separate-array or unknown variant launched on the interleaved copy");
     }

@@ -352,7 +352,7 @@ def test_every_sweep_variant_gives_the_same_bits(width):
     ref = {}
     ran = 0
     try:
-        for cfg in range(25):
+        for cfg in range(36):
             os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
             for dt in (torch.float64, torch.float32):
                 try:
@@ -362,7 +362,7 @@ def test_every_sweep_variant_gives_the_same_bits(width):
                     continue
                 ran += 1
                 name = M.sweep_config("f64" if dt == torch.float64 else "f32")
-                assert name.startswith(("row/", "lds/", "ell/", "ell2/"))
+                assert name.startswith(("row/", "lds/", "ell/", "ell2/", "row2/"))
                 if name.startswith(("ell/", "ell2/")):
                     assert f"/w{width}/" in name
                 ref.setdefault(str(dt), (x, y))
@@ -371,7 +371,7 @@ def test_every_sweep_variant_gives_the_same_bits(width):
                     assert np.max(np.abs(x - ex)) <= TOL64 * extent(m.xy)
     finally:
         os.environ.pop("LMS_SWEEP_CONFIG", None)
-    assert ran >= 2 * 12
+    assert ran >= 2 * 17
 
 
 def test_autotuned_sweep_matches_oracle_and_reports_choice():
@@ -381,7 +381,7 @@ def test_autotuned_sweep_matches_oracle_and_reports_choice():
     ex, ey = osm.jacobi(top, m.x, m.y, 6)
     x, y, _, M = run_library(m, "bfs", 6)
     name = M.sweep_config("f64")
-    assert name.split("/")[0] in ("row", "lds", "ell", "ell2")
+    assert name.split("/")[0] in ("row", "lds", "ell", "ell2", "row2")
     assert "tuned[" in name and M.sweep_config("f32") == ""
     M.reorder("random", seed=1)                  # a new ordering is tuned afresh
     assert M.sweep_config("f64") == "" and isinstance(lms.ORI, int)
