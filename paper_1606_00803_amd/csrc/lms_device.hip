@@ -437,6 +437,46 @@ __global__ __launch_bounds__(256) void k_colour(const int32_t *__restrict__ row_
     y[v] = ay / c;
 }
 
+// Multicolour sweep of one colour on the interleaved copy, in place.  The
+// colour's vertices read their neighbours' current positions (none of which
+// has this colour) through the colour-major padded index: entry k of the
+// colour's i-th vertex at cell[k*cnt + i].  Same order of additions as
+// k_colour, same bits.
+template <typename T, int BS, int W>
+__global__ __launch_bounds__(BS) void k_colour2(const int32_t *__restrict__ list, const int32_t *__restrict__ cell,
+                                                int32_t cnt, vec2_t<T> *xy, const StopState *__restrict__ st) {
+    if (st && st->done) return;
+    const int32_t i = int32_t(blockIdx.x) * BS + int32_t(threadIdx.x);
+    if (i >= cnt) return;
+    int32_t u[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) u[k] = __builtin_nontemporal_load(cell + int64_t(k) * cnt + i);
+    const int32_t v = list[i];
+    vec2_t<T> p[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        if (u[k] >= 0) {
+            p[k] = xy[u[k]];
+        } else {
+            p[k].x = T(0);
+            p[k].y = T(0);
+        }
+    }
+    T ax = T(0), ay = T(0);
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        if (u[k] >= 0) {
+            ax += p[k].x;
+            ay += p[k].y;
+            ++c;
+        }
+    vec2_t<T> o;
+    o.x = ax / T(c);
+    o.y = ay / T(c);
+    xy[v] = o;
+}
+
 // ---------------------------------------------------------------------------
 // Quality (Section 3.2) of one triangle: shortest / longest Euclidean edge.
 __device__ __forceinline__ double tri_quality(double xa, double ya, double xb, double yb, double xc,
@@ -672,6 +712,7 @@ struct DeviceState {
     std::vector<void *> arrays;  // mesh arrays of the current version
     int32_t *row_ptr = nullptr, *col = nullptr, *color_list = nullptr, *new2old = nullptr;
     int32_t *ell = nullptr;  // padded adjacency (column-major), when the handle has one
+    int32_t *color_ell = nullptr;  // colour-major padded adjacency
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
     double *tw = nullptr;
     int64_t *t_off = nullptr, *v_off = nullptr;
@@ -754,6 +795,7 @@ DeviceState &ensure_device(Mesh &M) {
         d->row_ptr = upload(d, M.row_ptr);
         d->col = upload(d, M.col);
         d->ell = M.ell_w > 0 ? upload(d, M.ell) : nullptr;
+        d->color_ell = M.ell_w > 0 ? upload(d, M.color_ell) : nullptr;
         d->color_list = upload(d, M.color_list);
         d->new2old = upload(d, M.new2old);
         d->ta = upload(d, M.ta);
@@ -1114,6 +1156,30 @@ void launch_colour_sweep(const DeviceState &d, const Mesh &M, T *x, T *y, const 
 }
 
 template <typename T>
+void launch_colour_sweep2(const DeviceState &d, const Mesh &M, vec2_t<T> *xy, const StopState *st, hipStream_t s) {
+    for (int32_t c = 0; c < M.n_colors; ++c) {
+        const int32_t b = M.color_ptr[c], cnt = M.color_ptr[c + 1] - b;
+        if (cnt == 0) continue;
+        const int32_t *list = d.color_list + b;
+        const int32_t *cell = d.color_ell + int64_t(M.ell_w) * b;
+        const int g = (cnt + 255) / 256;
+        switch (M.ell_w) {
+            case 8:
+                k_colour2<T, 256, 8><<<g, 256, 0, s>>>(list, cell, cnt, xy, st);
+                break;
+            case 12:
+                k_colour2<T, 256, 12><<<g, 256, 0, s>>>(list, cell, cnt, xy, st);
+                break;
+            case 16:
+                k_colour2<T, 256, 16><<<g, 256, 0, s>>>(list, cell, cnt, xy, st);
+                break;
+            default:
+                fail(LMS_ERR_STATE, "no padded colour index for this mesh");
+        }
+    }
+}
+
+template <typename T>
 void launch_quality(const DeviceState &d, const Mesh &M, const T *x, const T *y, double *qt_out,
                     const StopState *st, hipStream_t s, const vec2_t<T> *xy = nullptr) {
     k_quality<T, kQualBS><<<quality_blocks(M.T), kQualBS, 0, s>>>(d.ta, d.tb, d.tc, d.tw, x, y, xy, M.T,
@@ -1198,24 +1264,27 @@ bool overlaps(const void *a, const void *b, size_t bytes) {
 // lms_smooth on the interleaved working copies: pack P_0 into both copies,
 // sweep back and forth between them (graph-captured), unpack the last one.
 template <typename T>
-void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, const lms_smooth_opts &o, hipStream_t s,
-                   lms_smooth_result &r) {
+void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_scheme sch, const lms_smooth_opts &o,
+                   hipStream_t s, lms_smooth_result &r) {
     const int pi = sizeof(T) == 8 ? 0 : 1;
-    const int cfg = d.smooth_cfg[pi];
+    const bool colour = sch == LMS_MULTICOLOR;
+    const int cfg = colour ? -1 : d.smooth_cfg[pi];
     vec2_t<T> *A = ensure_packed<T>(d, 0, M.n);
     vec2_t<T> *B = ensure_packed<T>(d, 1, M.n);
     const int nb = (M.n + 255) / 256;
-    k_pack<T><<<nb, 256, 0, s>>>(x, y, A, B, M.n);
+    k_pack<T><<<nb, 256, 0, s>>>(x, y, A, colour ? nullptr : B, M.n);
     launch_check();
     const std::string base = std::string("packed|") + (p == LMS_FP64 ? "f64" : "f32") + "|" + ptr_key(A) + "|" +
-                             ptr_key(B) + "|cfg" + std::to_string(cfg);
+                             ptr_key(B) + "|cfg" + std::to_string(cfg) + "|" + std::to_string(int(sch));
     int32_t iters = 0;
     if (!o.check_quality) {
         const int32_t K = o.max_iters;
         if (K > 0)
             run_maybe_graph(d, "fixed|" + base + "|" + std::to_string(K), s, [&](hipStream_t cs) {
                 for (int32_t k = 0; k < K; ++k) {
-                    if (k % 2 == 0)
+                    if (colour)
+                        launch_colour_sweep2<T>(d, M, A, nullptr, cs);
+                    else if (k % 2 == 0)
                         launch_sweep2_cfg<T>(cfg, d, M, A, B, nullptr, cs);
                     else
                         launch_sweep2_cfg<T>(cfg, d, M, B, A, nullptr, cs);
@@ -1238,7 +1307,12 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, const l
             run_maybe_graph(d, key, s, [&](hipStream_t cs) {
                 for (int k = 0; k < kChunk; ++k) {
                     vec2_t<T> *src = k % 2 == 0 ? A : B, *dst = k % 2 == 0 ? B : A;
-                    launch_sweep2_cfg<T>(cfg, d, M, src, dst, d.st, cs);
+                    if (colour) {
+                        launch_colour_sweep2<T>(d, M, A, d.st, cs);
+                        dst = A;
+                    } else {
+                        launch_sweep2_cfg<T>(cfg, d, M, src, dst, d.st, cs);
+                    }
                     launch_quality<T>(d, M, nullptr, nullptr, nullptr, d.st, cs, dst);
                     launch_stop(d, M, 0, o, cs);
                 }
@@ -1251,7 +1325,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, const l
         r.q_final = h.q_last;
         r.last_dq = h.last_dq;
     }
-    k_unpack<T><<<nb, 256, 0, s>>>(iters % 2 == 1 ? B : A, x, y, M.n);
+    k_unpack<T><<<nb, 256, 0, s>>>(!colour && iters % 2 == 1 ? B : A, x, y, M.n);
     launch_check();
     HIP_CHECK(hipStreamSynchronize(s));
     r.iters = iters;
@@ -1263,9 +1337,12 @@ void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precisi
     if (sch == LMS_JACOBI) {
         tune_sweep<T>(d, M, x, y, tx, ty, s);
         if (sweep_config_packed(d.smooth_cfg[sizeof(T) == 8 ? 0 : 1])) {
-            smooth_packed<T>(M, d, x, y, p, o, s, r);
+            smooth_packed<T>(M, d, x, y, p, sch, o, s, r);
             return;
         }
+    } else if (M.ell_w > 0 && env_flag("LMS_PACKED_COLOUR", true)) {
+        smooth_packed<T>(M, d, x, y, p, sch, o, s, r);
+        return;
     }
     const std::string base = std::string(p == LMS_FP64 ? "f64" : "f32") + "|" + ptr_key(x) + "|" +
                              ptr_key(y) + "|" + ptr_key(tx) + "|" + ptr_key(ty) + "|cfg" +

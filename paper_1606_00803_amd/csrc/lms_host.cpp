@@ -348,6 +348,22 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
             if (color[k] >= 0) color_list[fill[color[k]]++] = k;
     }
 
+    // colour-major padded copy for the multicolour sweep: one coalesced index
+    // load per entry for the vertices of one colour
+    std::vector<int32_t> color_ell;
+    if (ell_w > 0) {
+        resize_or_fail(color_ell, size_t(ell_w) * color_list.size());
+        std::fill(color_ell.begin(), color_ell.end(), -1);
+        for (int32_t c = 0; c < M.n_colors; ++c) {
+            const int64_t base = int64_t(ell_w) * color_ptr[c], cnt = color_ptr[c + 1] - color_ptr[c];
+            for (int64_t i = 0; i < cnt; ++i) {
+                const int32_t k = color_list[size_t(color_ptr[c] + i)];
+                for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j)
+                    color_ell[size_t(base + int64_t(j - row_ptr[k]) * cnt + i)] = col[j];
+            }
+        }
+    }
+
     // triangles: counting sort by smallest new id, stable in input index
     const int64_t T = M.T;
     std::vector<int64_t> bucket(size_t(n) + 1, 0);
@@ -402,6 +418,7 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
     M.color = std::move(color);
     M.color_ptr = std::move(color_ptr);
     M.color_list = std::move(color_list);
+    M.color_ell = std::move(color_ell);
     M.ta = std::move(ta);
     M.tb = std::move(tb);
     M.tc = std::move(tc);

@@ -59,6 +59,9 @@ struct Mesh {
     std::vector<int32_t> color;             // n
     std::vector<int32_t> color_ptr;         // n_colors+1
     std::vector<int32_t> color_list;        // free vertices grouped by colour, ascending
+    std::vector<int32_t> color_ell;         // colour-major padded neighbours: for the vertex at
+                                            // color_list[color_ptr[c] + i], entry k sits at
+                                            // color_ell[ell_w*color_ptr[c] + k*cnt_c + i] (-1 past the row)
     std::vector<int32_t> ta, tb, tc;        // triangles (current labels), sorted for locality
     std::vector<double> tw;                 // per-triangle weight of the global mean
     std::vector<int32_t> tmesh;             // mesh index of each triangle (current order)

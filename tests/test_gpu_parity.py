@@ -408,3 +408,24 @@ def test_graded16m_full_size_sampled_parity():
     x32, y32, _, _ = run_library(m, "rdr", K, dtype=torch.float32, M=M)
     d = np.hypot(x32[sample] - ex, y32[sample] - ey) / e
     assert d.max() <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_multicolour_interleaved_and_separate_paths_agree(prec):
+    # the in-place colour sweep on the interleaved copy (default) and on the
+    # separate x, y arrays give the same bits, with and without the stop rule
+    torch = torch_mod()
+    m = meshgen.jittered_grid(211, 157, seed=21, land_fraction=0.3)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    outs = []
+    for flag in ("1", "0"):
+        os.environ["LMS_PACKED_COLOUR"] = flag
+        try:
+            a = run_library(m, "rdr", 9, dtype=dt, scheme="multicolor")
+            b = run_library(m, "bfs", 500, dtype=dt, scheme="multicolor", check_quality=True)
+        finally:
+            os.environ.pop("LMS_PACKED_COLOUR", None)
+        outs.append((a, b))
+    (a1, b1), (a0, b0) = outs
+    assert np.array_equal(a1[0], a0[0]) and np.array_equal(a1[1], a0[1])
+    assert np.array_equal(b1[0], b0[0]) and b1[2]["iters"] == b0[2]["iters"]
