@@ -239,6 +239,8 @@ def bench_ocean(torch, args):
         x0 = torch.as_tensor(m.x, dtype=torch.float64, device="cuda")
         y0 = torch.as_tensor(m.y, dtype=torch.float64, device="cuda")
         M.permute(x0, y0, x, y)
+        M.smooth(x, y, max_iters=2000, tol=5e-6)          # tunes and captures the graphs
+        M.permute(x0, y0, x, y)
         with Timer(torch) as t:
             rr = M.smooth(x, y, max_iters=2000, tol=5e-6)
         extras["to_criterion_rdr_f64"] = dict(iters=rr["iters"], stopped_by=rr["stopped_by"], q0=rr["q0"],
@@ -300,6 +302,21 @@ def bench_graded16m(torch, args):
                 finals[prec] = (x0.double().cpu().numpy(), y0.double().cpu().numpy())
             del x, y
     extras = dict(host_seconds=dict(generate=t_gen, **{f"reorder_{k}": v for k, v in reorder_s.items()}))
+    # the quality pass (Section 3.2) on the last ordering, float64 and float32
+    for prec in ("f64", "f32"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        x = torch.as_tensor(m.x, dtype=dt, device="cuda")
+        y = torch.as_tensor(m.y, dtype=dt, device="cuda")
+        M.quality(x, y)
+        with Timer(torch) as t:
+            for _ in range(10):
+                M.quality(x, y)
+        qb = quality_bytes(info["n"], m.T, 8 if prec == "f64" else 4)
+        us = t.ms * 1e3 / 10
+        extras[f"quality_pass_{prec}"] = dict(us_per_call=us, algorithmic_bytes=qb,
+                                              achieved_gbs=qb / (us * 1e-6) / 1e9)
+        log(f"quality pass {prec}: {us:.1f} us/call (incl. host read-back), {qb / (us * 1e-6) / 1e9:.0f} GB/s")
+        del x, y
     cpu = None
     if not args.no_cpu_baseline and "f32" in finals:
         cpu, top = cpu_baseline(m, SWEEPS, budget_s=0.0)

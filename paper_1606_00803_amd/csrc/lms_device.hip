@@ -218,10 +218,57 @@ __global__ __launch_bounds__(BS) void k_jacobi_row(const int32_t *__restrict__ r
     }
 }
 
-// Jacobi sweep over the padded ("ELL") copy of the adjacency: entry k of
-// every row sits at ell[k*n + v] (-1 past the row's end), so a thread finds
-// its neighbours without first reading row offsets, and every index load of
-// a wavefront is one coalesced line.  Rows have at most W entries.  Each
+// Vector loads of one row's padded entries: a row of W int32 indices (W a
+// multiple of 4, 16-byte aligned) or of W uint16 slots (W*2 bytes, 16-byte
+// aligned for W = 8, 16 and 8-byte aligned for W = 12), with the
+// non-temporal hint.  One or two loads per lane instead of W.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int W>
+__device__ __forceinline__ void load_row_ids(const int32_t *__restrict__ row, int32_t (&u)[W]) {
+    static_assert(W % 4 == 0, "padded width must be a multiple of 4");
+#pragma unroll
+    for (int q = 0; q < W / 4; ++q) {
+        const i32x4 v = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(row) + q);
+        u[4 * q] = v.x;
+        u[4 * q + 1] = v.y;
+        u[4 * q + 2] = v.z;
+        u[4 * q + 3] = v.w;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void load_row_slots(const uint16_t *__restrict__ row, uint16_t (&s)[W]) {
+    if constexpr (W % 8 == 0) {
+#pragma unroll
+        for (int q = 0; q < W / 8; ++q) {
+            const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row) + q);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                s[8 * q + 2 * i] = uint16_t(w[i] & 0xFFFFu);
+                s[8 * q + 2 * i + 1] = uint16_t(w[i] >> 16);
+            }
+        }
+    } else {
+        static_assert(W % 4 == 0, "padded width must be a multiple of 4");
+#pragma unroll
+        for (int q = 0; q < W / 4; ++q) {
+            const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(row) + q);
+            s[4 * q] = uint16_t(v.x & 0xFFFFu);
+            s[4 * q + 1] = uint16_t(v.x >> 16);
+            s[4 * q + 2] = uint16_t(v.y & 0xFFFFu);
+            s[4 * q + 3] = uint16_t(v.y >> 16);
+        }
+    }
+}
+
+// Jacobi sweep over the padded ("ELL") copy of the adjacency: row v's W
+// entries sit together at ell[v*W ..] (-1 past the row's end), so a thread
+// finds its neighbours without first reading row offsets, with W/4 16-byte
+// loads that are coalesced across the wavefront.  Rows have at most W entries.  Each
 // thread owns R rows BS apart.  Entries are in the CSR order: same bits.
 template <typename T, int BS, int W, int R, int MAP>
 __global__ __launch_bounds__(BS) void k_jacobi_ell(const int32_t *__restrict__ ell,
@@ -236,9 +283,12 @@ __global__ __launch_bounds__(BS) void k_jacobi_ell(const int32_t *__restrict__ e
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int32_t v = v0 + r * BS;
+        if (v < n) {
+            load_row_ids<W>(ell + int64_t(v) * W, u[r]);
+        } else {
 #pragma unroll
-        for (int k = 0; k < W; ++k)
-            u[r][k] = v < n ? __builtin_nontemporal_load(ell + int64_t(k) * n + v) : -1;
+            for (int k = 0; k < W; ++k) u[r][k] = -1;
+        }
     }
     T vx[R][W], vy[R][W];
 #pragma unroll
@@ -318,9 +368,12 @@ __global__ __launch_bounds__(BS) void k_jacobi_ell2(const int32_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int32_t v = v0 + r * BS;
+        if (v < n) {
+            load_row_ids<W>(ell + int64_t(v) * W, u[r]);
+        } else {
 #pragma unroll
-        for (int k = 0; k < W; ++k)
-            u[r][k] = v < n ? __builtin_nontemporal_load(ell + int64_t(k) * n + v) : -1;
+            for (int k = 0; k < W; ++k) u[r][k] = -1;
+        }
     }
     vec2_t<T> p[R][W];
 #pragma unroll
@@ -437,6 +490,62 @@ __global__ __launch_bounds__(256) void k_colour(const int32_t *__restrict__ row_
     y[v] = ay / c;
 }
 
+// Jacobi sweep with the tile's neighbourhood staged in LDS.  Workgroup t owns
+// rows [t*TS, (t+1)*TS): it loads their coordinates (coalesced) and those of
+// the tile's halo (the sorted outside neighbours, one load each) into LDS
+// once; each row then reads its W neighbours from LDS through 16-bit
+// tile-local slots (0xFFFF past the row's end; one 16-byte load per row for
+// W = 8).  Every global gather of the
+// other variants becomes an LDS read, and the index stream halves.  Entries
+// keep the row's ascending order: same additions, same bits.
+template <typename T, int TS, int W, int MAP>
+__global__ __launch_bounds__(TS) void k_jacobi_halo(const int32_t *__restrict__ halo_ptr,
+                                                    const int32_t *__restrict__ halo,
+                                                    const uint16_t *__restrict__ lidx,
+                                                    const vec2_t<T> *__restrict__ src,
+                                                    vec2_t<T> *__restrict__ dst, int32_t n,
+                                                    const StopState *__restrict__ st) {
+    extern __shared__ unsigned char lds_raw[];
+    vec2_t<T> *stage = reinterpret_cast<vec2_t<T> *>(lds_raw);
+    if (st && st->done) return;
+    const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
+    const int tid = int(threadIdx.x);
+    const int32_t v = tile * TS + tid;
+    uint16_t li[W];
+    load_row_slots<W>(lidx + (int64_t(tile) * TS + tid) * W, li);
+    if (v < n) stage[tid] = src[v];
+    const int32_t hb = halo_ptr[tile], he = halo_ptr[tile + 1];
+    for (int32_t j0 = hb + tid; j0 < he; j0 += 4 * TS) {
+        int32_t g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = j0 + q * TS < he ? halo[j0 + q * TS] : -1;
+        vec2_t<T> h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (g[q] >= 0) h[q] = src[g[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (g[q] >= 0) stage[TS + (j0 + q * TS - hb)] = h[q];
+    }
+    __syncthreads();
+    T ax = T(0), ay = T(0);
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        if (li[k] != 0xFFFF) {
+            const vec2_t<T> p = stage[li[k]];
+            ax += p.x;
+            ay += p.y;
+            ++c;
+        }
+    if (c > 0) {
+        vec2_t<T> o;
+        o.x = ax / T(c);
+        o.y = ay / T(c);
+        dst[v] = o;
+    }
+}
+
 // Multicolour sweep of one colour on the interleaved copy, in place.  The
 // colour's vertices read their neighbours' current positions (none of which
 // has this colour) through the colour-major padded index: entry k of the
@@ -539,17 +648,51 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
 
 // Per-block partial sums of q_t * w_t over a grid-stride range of triangles,
 // where w_t = sum over the corners of 1/|T(v)| (the 1/|V| of the global mean
-// is applied by the final reduction).  Optionally stores q_t.
+// is applied by the final reduction).  Optionally stores q_t.  Each triangle
+// is one 16-byte record (corners a, b, c; counts |T(v)| packed 10 bits each,
+// from which w_t is recomputed in the same order as on the host); each thread
+// takes four triangles per step, loads first.
 template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_quality(const int32_t *__restrict__ ta,
-                                                const int32_t *__restrict__ tb,
-                                                const int32_t *__restrict__ tc,
-                                                const double *__restrict__ tw,
-                                                const T *__restrict__ x, const T *__restrict__ y,
-                                                const vec2_t<T> *__restrict__ xy,
+__global__ __launch_bounds__(BS) void k_quality(const int32_t *__restrict__ trec, const T *__restrict__ x,
+                                                const T *__restrict__ y, const vec2_t<T> *__restrict__ xy,
                                                 int64_t ntri, double *__restrict__ partials,
-                                                double *__restrict__ qt_out,
-                                                const StopState *__restrict__ st) {
+                                                double *__restrict__ qt_out, const StopState *__restrict__ st) {
+    __shared__ double s_red[BS / 64];
+    if (st && st->done) return;
+    double acc = 0.0;
+    const int64_t stride = int64_t(gridDim.x) * BS;
+    for (int64_t t0 = int64_t(blockIdx.x) * BS + threadIdx.x; t0 < ntri; t0 += 4 * stride) {
+        i32x4 r[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t t = t0 + q * stride;
+            if (t < ntri) r[q] = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(trec) + t);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t t = t0 + q * stride;
+            if (t < ntri) {
+                const double qt = tri_quality_at(x, y, xy, r[q].x, r[q].y, r[q].z);
+                const uint32_t cnt = uint32_t(r[q].w);
+                const double w = 1.0 / double(cnt & 1023u) + 1.0 / double((cnt >> 10) & 1023u) +
+                                 1.0 / double(cnt >> 20);
+                if (qt_out) qt_out[t] = qt;
+                acc += qt * w;
+            }
+        }
+    }
+    const double s = block_sum<BS>(acc, s_red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// The same without the packed record (a vertex in more than 1023 triangles).
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_quality_wide(const int32_t *__restrict__ ta, const int32_t *__restrict__ tb,
+                                                     const int32_t *__restrict__ tc, const double *__restrict__ tw,
+                                                     const T *__restrict__ x, const T *__restrict__ y,
+                                                     const vec2_t<T> *__restrict__ xy, int64_t ntri,
+                                                     double *__restrict__ partials, double *__restrict__ qt_out,
+                                                     const StopState *__restrict__ st) {
     __shared__ double s_red[BS / 64];
     if (st && st->done) return;
     double acc = 0.0;
@@ -689,7 +832,7 @@ __global__ __launch_bounds__(256) void k_permute(const int32_t *__restrict__ new
 namespace {
 
 constexpr int kQualBS = 256;
-constexpr int kQualMaxBlocks = 1024;
+constexpr int kQualMaxBlocks = 8192;
 constexpr int kChunk = 16;  // sweeps per captured chunk under the stopping rule (even)
 
 struct GraphEntry {
@@ -713,8 +856,15 @@ struct DeviceState {
     int32_t *row_ptr = nullptr, *col = nullptr, *color_list = nullptr, *new2old = nullptr;
     int32_t *ell = nullptr;  // padded adjacency (column-major), when the handle has one
     int32_t *color_ell = nullptr;  // colour-major padded adjacency
+    struct HaloDev {
+        int32_t ts = 0, h_max = 0;
+        int32_t *halo_ptr = nullptr, *halo = nullptr;
+        uint16_t *lidx = nullptr;
+    };
+    std::vector<HaloDev> halos;  // uploaded tile plans of the current version
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
     double *tw = nullptr;
+    int32_t *trec = nullptr;
     int64_t *t_off = nullptr, *v_off = nullptr;
     // scratch, kept across versions
     double *partials = nullptr;
@@ -763,7 +913,7 @@ T *upload(DeviceState *d, const std::vector<T> &v) {
 }
 
 int quality_blocks(int64_t ntri) {
-    const int64_t need = (ntri + kQualBS - 1) / kQualBS;
+    const int64_t need = (ntri + 4 * kQualBS - 1) / (4 * kQualBS);
     return int(std::max<int64_t>(1, std::min<int64_t>(need, kQualMaxBlocks)));
 }
 
@@ -791,6 +941,7 @@ DeviceState &ensure_device(Mesh &M) {
     if (d->version != M.version) {
         free_graphs(d);
         free_arrays(d);
+        d->halos.clear();  // their arrays were in d->arrays
         d->version = ~uint64_t(0);
         d->row_ptr = upload(d, M.row_ptr);
         d->col = upload(d, M.col);
@@ -802,6 +953,7 @@ DeviceState &ensure_device(Mesh &M) {
         d->tb = upload(d, M.tb);
         d->tc = upload(d, M.tc);
         d->tw = upload(d, M.tw);
+        d->trec = M.trec.empty() ? nullptr : upload(d, M.trec);
         d->vt_ptr = upload(d, M.vt_ptr);
         d->vt = upload(d, M.vt);
         d->t_off = upload(d, M.t_off);
@@ -839,7 +991,9 @@ void launch_check() {
 //   ELL(id, BS, W, R, MAP)       k_jacobi_ell (eligible when the padded width is W)
 //   ELL2(id, BS, W, R, MAP)      k_jacobi_ell2 on the interleaved copy (lms_smooth only)
 //   ROW2(id, BS, U, R, MAP)      k_jacobi_row2 on the interleaved copy (lms_smooth only)
-#define LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2) \
+//   HALO(id, TS, W, MAP)         k_jacobi_halo on the interleaved copy (lms_smooth only;
+//                                eligible when the padded width is W and the staging fits)
+#define LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2, HALO) \
     ROW(0, 256, 8, 1, -1, true)                  \
     ROW(1, 256, 8, 1, 0, true)                   \
     ROW(2, 64, 8, 1, -1, true)                   \
@@ -875,8 +1029,16 @@ void launch_check() {
     ROW2(32, 128, 8, 2, 0)                       \
     ROW2(33, 256, 8, 1, -1)                      \
     ROW2(34, 128, 8, 1, 16)                      \
-    ROW2(35, 64, 8, 1, 0)
-constexpr int kNumSweepConfigs = 36;
+    ROW2(35, 64, 8, 1, 0)                        \
+    HALO(36, 256, 8, 0)                          \
+    HALO(37, 256, 8, 16)                         \
+    HALO(38, 256, 8, -1)                         \
+    HALO(39, 128, 8, 0)                          \
+    HALO(40, 512, 8, 0)                          \
+    HALO(41, 128, 8, 16)                         \
+    HALO(42, 256, 12, 0)                         \
+    HALO(43, 256, 16, 0)
+constexpr int kNumSweepConfigs = 44;
 constexpr int kDefaultSweepConfig = 0;
 
 std::string map_name(int map) {
@@ -907,12 +1069,17 @@ std::string sweep_config_name(int cfg) {
     case id:                                                                                      \
         std::snprintf(buf, sizeof(buf), "row2/bs%d/u%d/r%d/%s", bs, u, r, map_name(map).c_str()); \
         return buf;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
+#define HALO(id, ts, w, map)                                                                      \
+    case id:                                                                                      \
+        std::snprintf(buf, sizeof(buf), "halo/ts%d/w%d/%s", ts, w, map_name(map).c_str());       \
+        return buf;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2, HALO)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
 #undef ROW2
+#undef HALO
     }
     return "unknown";
 }
@@ -935,12 +1102,16 @@ int sweep_config_ell_width(int cfg) {
 #define ROW2(id, bs, u, r, map) \
     case id:                    \
         return 0;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
+#define HALO(id, ts, w, map) \
+    case id:                 \
+        return w;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2, HALO)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
 #undef ROW2
+#undef HALO
     }
     return -1;
 }
@@ -963,14 +1134,40 @@ bool sweep_config_packed(int cfg) {
 #define ROW2(id, bs, u, r, map) \
     case id:                    \
         return true;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
+#define HALO(id, ts, w, map) \
+    case id:                 \
+        return true;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2, HALO)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
 #undef ROW2
+#undef HALO
     }
     return false;
+}
+
+int sweep_config_tile(int cfg) {
+    switch (cfg) {
+#define ROW(id, bs, u, r, map, nt)
+#define LDS(id, bs, cap, map)
+#define ELL(id, bs, w, r, map)
+#define ELL2(id, bs, w, r, map)
+#define ROW2(id, bs, u, r, map)
+#define HALO(id, ts, w, map) \
+    case id:                 \
+        return ts;
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2, HALO)
+#undef ROW
+#undef LDS
+#undef ELL
+#undef ELL2
+#undef ROW2
+#undef HALO
+        default:
+            return 0;
+    }
 }
 
 bool sweep_config_eligible(int cfg, const Mesh &M) {
@@ -979,6 +1176,39 @@ bool sweep_config_eligible(int cfg, const Mesh &M) {
 }
 
 int grid_for(int64_t n, int rows_per_block) { return int((n + rows_per_block - 1) / rows_per_block); }
+
+const DeviceState::HaloDev *find_halo(const DeviceState &d, int32_t ts) {
+    for (const auto &h : d.halos)
+        if (h.ts == ts) return &h;
+    return nullptr;
+}
+
+// Build (host) and upload the tile plan of the halo-staged sweep for tile size ts.
+const DeviceState::HaloDev &ensure_halo(DeviceState &d, Mesh &M, int32_t ts) {
+    if (const DeviceState::HaloDev *h = find_halo(d, ts)) return *h;
+    const Mesh::HaloPlan &P = halo_plan(M, ts);
+    DeviceState::HaloDev h;
+    h.ts = ts;
+    h.h_max = P.h_max;
+    h.halo_ptr = upload(&d, P.halo_ptr);
+    h.halo = upload(&d, P.halo);
+    h.lidx = upload(&d, P.lidx);
+    d.halos.push_back(h);
+    return d.halos.back();
+}
+
+int sweep_config_tile(int cfg);  // tile size of a halo-staged variant, 0 otherwise
+
+// Whether variant cfg can run on this mesh in precision T (builds the tile
+// plan of a halo-staged variant on first use).
+template <typename T>
+bool sweep_config_usable(int cfg, DeviceState &d, Mesh &M) {
+    if (!sweep_config_eligible(cfg, M)) return false;
+    const int ts = sweep_config_tile(cfg);
+    if (ts == 0) return true;
+    const DeviceState::HaloDev &h = ensure_halo(d, M, ts);
+    return size_t(ts + h.h_max) * sizeof(vec2_t<T>) <= size_t(64) * 1024;
+}
 
 template <typename T>
 void launch_sweep_cfg(int cfg, const DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
@@ -1001,12 +1231,14 @@ void launch_sweep_cfg(int cfg, const DeviceState &d, const Mesh &M, const T *sx,
         break;
 #define ELL2(id, bs, w, r, map)
 #define ROW2(id, bs, u, r, map)
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
+#define HALO(id, ts, w, map)
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2, HALO)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
 #undef ROW2
+#undef HALO
         default:
             fail(LMS_ERR_STATE, "interleaved or unknown variant launched on separate x, y arrays");
     }
@@ -1030,12 +1262,21 @@ void launch_sweep2_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_
         k_jacobi_row2<T, bs, u, r, map><<<grid_for(n, bs * r), bs, 0, s>>>(d.row_ptr, d.col, src, dst,    \
                                                                            M.n, st);                      \
         break;
-        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2)
+#define HALO(id, ts, w, map)                                                                               \
+    case id: {                                                                                             \
+        const DeviceState::HaloDev *h = find_halo(d, ts);                                                  \
+        if (!h || M.ell_w != w) fail(LMS_ERR_STATE, "halo-staged variant launched without its tile plan"); \
+        k_jacobi_halo<T, ts, w, map><<<grid_for(n, ts), ts, size_t(ts + h->h_max) * sizeof(vec2_t<T>), s>>>( \
+            h->halo_ptr, h->halo, h->lidx, src, dst, M.n, st);                                             \
+        break;                                                                                             \
+    }
+        LMS_SWEEP_CONFIGS(ROW, LDS, ELL, ELL2, ROW2, HALO)
 #undef ROW
 #undef LDS
 #undef ELL
 #undef ELL2
 #undef ROW2
+#undef HALO
         default:
             fail(LMS_ERR_STATE, "separate-array or unknown variant launched on the interleaved copy");
     }
@@ -1069,13 +1310,13 @@ vec2_t<T> *ensure_packed(DeviceState &d, int which, int32_t n) {
 // ordering and this precision.  LMS_SWEEP_CONFIG=<id> forces a variant;
 // LMS_AUTOTUNE=0 keeps the default.
 template <typename T>
-void tune_sweep(DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, T *dy, hipStream_t s) {
+void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy, hipStream_t s) {
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (d.sweep_cfg[pi] >= 0) return;
     if (const char *f = std::getenv("LMS_SWEEP_CONFIG")) {
         const int c = std::atoi(f);
         if (c < 0 || c >= kNumSweepConfigs) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG out of range");
-        if (!sweep_config_eligible(c, M)) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG names a variant this mesh cannot use");
+        if (!sweep_config_usable<T>(c, d, M)) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG names a variant this mesh cannot use");
         d.sweep_cfg[pi] = sweep_config_packed(c) ? kDefaultSweepConfig : c;
         d.smooth_cfg[pi] = c;
         return;
@@ -1098,7 +1339,7 @@ void tune_sweep(DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, 
     hipError_t err = hipSuccess;
     vec2_t<T> *pa = nullptr, *pb = nullptr;
     for (int c = 0; c < kNumSweepConfigs && err == hipSuccess; ++c) {
-        if (!sweep_config_eligible(c, M)) {
+        if (!sweep_config_usable<T>(c, d, M)) {
             d.tune_us[pi][c] = -1.f;
             continue;
         }
@@ -1138,11 +1379,16 @@ void tune_sweep(DeviceState &d, const Mesh &M, const T *sx, const T *sy, T *dx, 
     launch_check();
     d.sweep_cfg[pi] = best;
     d.smooth_cfg[pi] = best_all;
-    if (env_flag("LMS_VERBOSE", false))
+    if (env_flag("LMS_VERBOSE", false)) {
         std::fprintf(stderr, "[lms] sweep autotune (%s, n=%d): %s, %.2f us (separate arrays: %s, %.2f us)\n",
                      pi == 0 ? "f64" : "f32", M.n, sweep_config_name(best_all).c_str(),
                      double(best_all_ms) * 1000.0 / reps, sweep_config_name(best).c_str(),
                      double(best_ms) * 1000.0 / reps);
+        for (int c = 0; c < kNumSweepConfigs; ++c)
+            if (d.tune_us[pi][c] >= 0.f)
+                std::fprintf(stderr, "[lms]   %2d %-28s %9.2f us\n", c, sweep_config_name(c).c_str(),
+                             double(d.tune_us[pi][c]));
+    }
 }
 
 template <typename T>
@@ -1182,8 +1428,11 @@ void launch_colour_sweep2(const DeviceState &d, const Mesh &M, vec2_t<T> *xy, co
 template <typename T>
 void launch_quality(const DeviceState &d, const Mesh &M, const T *x, const T *y, double *qt_out,
                     const StopState *st, hipStream_t s, const vec2_t<T> *xy = nullptr) {
-    k_quality<T, kQualBS><<<quality_blocks(M.T), kQualBS, 0, s>>>(d.ta, d.tb, d.tc, d.tw, x, y, xy, M.T,
-                                                                   d.partials, qt_out, st);
+    if (d.trec)
+        k_quality<T, kQualBS><<<quality_blocks(M.T), kQualBS, 0, s>>>(d.trec, x, y, xy, M.T, d.partials, qt_out, st);
+    else
+        k_quality_wide<T, kQualBS><<<quality_blocks(M.T), kQualBS, 0, s>>>(d.ta, d.tb, d.tc, d.tw, x, y, xy, M.T,
+                                                                        d.partials, qt_out, st);
 }
 
 void launch_stop(const DeviceState &d, const Mesh &M, int init, const lms_smooth_opts &o, hipStream_t s) {

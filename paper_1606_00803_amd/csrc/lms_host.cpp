@@ -326,7 +326,8 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
     }
 
     // padded copy of the smoothing adjacency for the offset-free sweep
-    // variant: width 8, 12 or 16 (the smallest that holds every row)
+    // variants, row-major (entry k of row v at ell[v*W + k], -1 past the
+    // row's end): width 8, 12 or 16, the smallest that holds every row
     int32_t ell_w = 0;
     std::vector<int32_t> ell;
     if (M.max_degree <= 16) {
@@ -334,7 +335,7 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
         resize_or_fail(ell, size_t(ell_w) * size_t(n));
         std::fill(ell.begin(), ell.end(), -1);
         for (int32_t k = 0; k < n; ++k)
-            for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j) ell[size_t(j - row_ptr[k]) * size_t(n) + k] = col[j];
+            for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j) ell[size_t(k) * size_t(ell_w) + size_t(j - row_ptr[k])] = col[j];
     }
 
     std::vector<int32_t> color_ptr(size_t(M.n_colors) + 1, 0), color_list;
@@ -391,6 +392,24 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
         // mesh index: meshes own contiguous triangle ranges in input order
         tmesh[i] = int32_t(std::upper_bound(M.t_off.begin(), M.t_off.end(), t) - M.t_off.begin() - 1);
     }
+    // packed 16-byte triangle record for the quality pass: the corners and the
+    // three triangle counts, from which the pass recomputes w_t exactly as above
+    std::vector<int32_t> trec;
+    {
+        bool small = true;
+        for (int32_t v = 0; v < n && small; ++v) small = M.tcount0[v] <= 1023;
+        if (small) {
+            resize_or_fail(trec, size_t(4) * size_t(T));
+            for (int64_t i = 0; i < T; ++i) {
+                const int64_t t = torder[i];
+                const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
+                trec[4 * i] = ta[i];
+                trec[4 * i + 1] = tb[i];
+                trec[4 * i + 2] = tc[i];
+                trec[4 * i + 3] = M.tcount0[a] | (M.tcount0[b] << 10) | (M.tcount0[c] << 20);
+            }
+        }
+    }
     std::vector<int32_t> vt_ptr(size_t(n) + 1, 0), vt(static_cast<size_t>(3 * T));
     for (int64_t i = 0; i < T; ++i) {
         vt_ptr[ta[i] + 1]++;
@@ -407,6 +426,7 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
         }
     }
 
+    M.halo_plans.clear();
     M.ordering = kind;
     M.new2old = std::move(new2old);
     M.old2new = std::move(old2new);
@@ -423,10 +443,77 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
     M.tb = std::move(tb);
     M.tc = std::move(tc);
     M.tw = std::move(tw);
+    M.trec = std::move(trec);
     M.tmesh = std::move(tmesh);
     M.vt_ptr = std::move(vt_ptr);
     M.vt = std::move(vt);
     M.version++;
+}
+
+// Tile plan of the halo-staged sweep for tile size ts (see HaloPlan).  The
+// entries keep the row's ascending neighbour order, so the staged sweep adds
+// neighbours in the same order as every other variant.
+const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts) {
+    for (const auto &h : M.halo_plans)
+        if (h.ts == ts && h.version == M.version) return h;
+    if (M.ell_w <= 0) fail(LMS_ERR_STATE, "no padded adjacency for a halo plan");
+    Mesh::HaloPlan H;
+    H.ts = ts;
+    const int32_t n = M.n, W = M.ell_w;
+    const int64_t tiles = (int64_t(n) + ts - 1) / ts;
+    H.halo_ptr.assign(size_t(tiles) + 1, 0);
+    resize_or_fail(H.lidx, size_t(tiles) * size_t(W) * size_t(ts));
+    std::fill(H.lidx.begin(), H.lidx.end(), uint16_t(0xFFFF));
+    std::vector<int32_t> outside;
+    for (int64_t t = 0; t < tiles; ++t) {
+        const int32_t b = int32_t(t * ts), e = int32_t(std::min<int64_t>(int64_t(n), (t + 1) * int64_t(ts)));
+        outside.clear();
+        for (int32_t j = M.row_ptr[b]; j < M.row_ptr[e]; ++j)
+            if (M.col[j] < b || M.col[j] >= e) outside.push_back(M.col[j]);
+        std::sort(outside.begin(), outside.end());
+        outside.erase(std::unique(outside.begin(), outside.end()), outside.end());
+        if (int64_t(ts) + int64_t(outside.size()) > 0xFFFF) fail(LMS_ERR_STATE, "tile halo too large for 16-bit slots");
+        H.h_max = std::max<int32_t>(H.h_max, int32_t(outside.size()));
+        uint16_t *lt = H.lidx.data() + size_t(t) * size_t(W) * size_t(ts);
+        for (int32_t v = b; v < e; ++v)
+            for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                const int32_t u = M.col[j];
+                int32_t slot;
+                if (u >= b && u < e) {
+                    slot = u - b;
+                } else {
+                    slot = ts + int32_t(std::lower_bound(outside.begin(), outside.end(), u) - outside.begin());
+                }
+                lt[size_t(v - b) * size_t(W) + size_t(j - M.row_ptr[v])] = uint16_t(slot);
+            }
+        H.halo.insert(H.halo.end(), outside.begin(), outside.end());
+        if (H.halo.size() >= (size_t(1) << 31)) fail(LMS_ERR_STATE, "halo lists exceed 2^31 entries");
+        H.halo_ptr[size_t(t) + 1] = int32_t(H.halo.size());
+    }
+    // self-check: every slot names the CSR neighbour it stands for and lies
+    // inside the tile's staging area (own rows + its halo)
+    for (int64_t t = 0; t < tiles; ++t) {
+        const int32_t b = int32_t(t * ts), e = int32_t(std::min<int64_t>(int64_t(n), (t + 1) * int64_t(ts)));
+        const int32_t hb = H.halo_ptr[size_t(t)], hn = H.halo_ptr[size_t(t) + 1] - hb;
+        const uint16_t *lt = H.lidx.data() + size_t(t) * size_t(W) * size_t(ts);
+        for (int32_t r = 0; r < ts; ++r) {
+            const int32_t v = b + r;
+            const int32_t deg = v < e ? M.row_ptr[v + 1] - M.row_ptr[v] : 0;
+            for (int32_t k = 0; k < W; ++k) {
+                const uint16_t slot = lt[size_t(r) * size_t(W) + size_t(k)];
+                if (k >= deg) {
+                    if (slot != 0xFFFF) fail(LMS_ERR_STATE, "halo plan: padding slot in use");
+                    continue;
+                }
+                if (slot >= ts + hn) fail(LMS_ERR_STATE, "halo plan: slot outside the staging area");
+                const int32_t u = slot < ts ? b + slot : H.halo[size_t(hb + slot - ts)];
+                if (u != M.col[size_t(M.row_ptr[v] + k)]) fail(LMS_ERR_STATE, "halo plan: slot names the wrong vertex");
+            }
+        }
+    }
+    H.version = M.version;
+    M.halo_plans.push_back(std::move(H));
+    return M.halo_plans.back();
 }
 
 }  // namespace lms

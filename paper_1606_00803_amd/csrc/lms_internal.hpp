@@ -54,7 +54,7 @@ struct Mesh {
     std::vector<int32_t> row_ptr;           // n+1, smoothing adjacency
     std::vector<int32_t> col;               // nnz
     int32_t ell_w = 0;                      // padded width (8, 12 or 16), 0 = no padded copy
-    std::vector<int32_t> ell;               // ell[k*n + v]: entry k of row v, -1 past its end
+    std::vector<int32_t> ell;               // ell[v*ell_w + k]: entry k of row v, -1 past its end
     std::vector<uint8_t> fixed;             // n
     std::vector<int32_t> color;             // n
     std::vector<int32_t> color_ptr;         // n_colors+1
@@ -64,8 +64,27 @@ struct Mesh {
                                             // color_ell[ell_w*color_ptr[c] + k*cnt_c + i] (-1 past the row)
     std::vector<int32_t> ta, tb, tc;        // triangles (current labels), sorted for locality
     std::vector<double> tw;                 // per-triangle weight of the global mean
+    std::vector<int32_t> trec;              // 4 per triangle: corners a, b, c and the three
+                                            // triangle counts |T(v)| packed 10 bits each (empty
+                                            // when a count exceeds 1023)
     std::vector<int32_t> tmesh;             // mesh index of each triangle (current order)
     std::vector<int32_t> vt_ptr, vt;        // vertex -> triangles in current labels/order
+
+    // Tile plans of the halo-staged sweep, built on first use for a tile size
+    // and dropped by relabel().  Tile t owns rows [t*ts, (t+1)*ts); its halo is
+    // the sorted list of neighbours outside that range; lidx holds, per tile
+    // row and entry k (row-major, lidx[(t*ts + r)*ell_w + k]), the neighbour's slot in
+    // the tile's staging area: own rows at 0..ts-1, halo vertices from ts on,
+    // 0xFFFF past the row's end.
+    struct HaloPlan {
+        int32_t ts = 0;
+        int32_t h_max = 0;
+        std::vector<int32_t> halo_ptr;  // tiles+1
+        std::vector<int32_t> halo;      // concatenated halo lists
+        std::vector<uint16_t> lidx;     // tiles * ell_w * ts
+        uint64_t version = ~uint64_t(0);
+    };
+    std::vector<HaloPlan> halo_plans;
 
     // generation counter: bumped whenever the current labelling changes so
     // that device copies and captured graphs are refreshed
@@ -82,6 +101,7 @@ std::vector<int32_t> order_bfs(const Mesh &M);
 std::vector<int32_t> order_rdr(const Mesh &M, const double *q);
 std::vector<int32_t> order_random(const Mesh &M, uint64_t seed);
 void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old);
+const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 
 // ---- device runtime (lms_device.hip) ----
 void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,

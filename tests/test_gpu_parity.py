@@ -352,7 +352,7 @@ def test_every_sweep_variant_gives_the_same_bits(width):
     ref = {}
     ran = 0
     try:
-        for cfg in range(36):
+        for cfg in range(44):
             os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
             for dt in (torch.float64, torch.float32):
                 try:
@@ -362,8 +362,8 @@ def test_every_sweep_variant_gives_the_same_bits(width):
                     continue
                 ran += 1
                 name = M.sweep_config("f64" if dt == torch.float64 else "f32")
-                assert name.startswith(("row/", "lds/", "ell/", "ell2/", "row2/"))
-                if name.startswith(("ell/", "ell2/")):
+                assert name.startswith(("row/", "lds/", "ell/", "ell2/", "row2/", "halo/"))
+                if name.startswith(("ell/", "ell2/", "halo/")):
                     assert f"/w{width}/" in name
                 ref.setdefault(str(dt), (x, y))
                 assert np.array_equal(x, ref[str(dt)][0]) and np.array_equal(y, ref[str(dt)][1]), cfg
@@ -381,7 +381,7 @@ def test_autotuned_sweep_matches_oracle_and_reports_choice():
     ex, ey = osm.jacobi(top, m.x, m.y, 6)
     x, y, _, M = run_library(m, "bfs", 6)
     name = M.sweep_config("f64")
-    assert name.split("/")[0] in ("row", "lds", "ell", "ell2", "row2")
+    assert name.split("/")[0] in ("row", "lds", "ell", "ell2", "row2", "halo")
     assert "tuned[" in name and M.sweep_config("f32") == ""
     M.reorder("random", seed=1)                  # a new ordering is tuned afresh
     assert M.sweep_config("f64") == "" and isinstance(lms.ORI, int)
@@ -429,3 +429,19 @@ def test_multicolour_interleaved_and_separate_paths_agree(prec):
     (a1, b1), (a0, b0) = outs
     assert np.array_equal(a1[0], a0[0]) and np.array_equal(a1[1], a0[1])
     assert np.array_equal(b1[0], b0[0]) and b1[2]["iters"] == b0[2]["iters"]
+
+
+def test_quality_when_a_vertex_has_many_triangles():
+    # a vertex in more than 1023 triangles does not fit the packed triangle
+    # record: the pass falls back to separate corner and weight arrays
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    for k in (40, 3000):
+        m = meshgen.wheel(k, seed=k)
+        M = lms.Mesh.build_csr(m.n, m.tri)
+        x = to_dev(m.x, torch.float64)
+        y = to_dev(m.y, torch.float64)
+        qv = torch.empty(m.n, dtype=torch.float64, device="cuda")
+        Q = M.quality(x, y, q_vertex=qv)
+        assert abs(Q - oq.global_quality(m.x, m.y, m.tri, m.n)) <= 1e-12
+        assert np.max(np.abs(qv.cpu().numpy() - oq.vertex_quality(m.x, m.y, m.tri, m.n))) <= 1e-14
