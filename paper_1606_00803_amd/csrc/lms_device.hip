@@ -519,13 +519,25 @@ __global__ __launch_bounds__(TS) void k_jacobi_halo(const int32_t *__restrict__ 
         int32_t g[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) g[q] = j0 + q * TS < he ? halo[j0 + q * TS] : -1;
-        vec2_t<T> h[4];
+        T hx[4], hy[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            hx[q] = T(0);
+            hy[q] = T(0);
+            if (g[q] >= 0) {
+                const vec2_t<T> h = src[g[q]];
+                hx[q] = h.x;
+                hy[q] = h.y;
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (g[q] >= 0) h[q] = src[g[q]];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (g[q] >= 0) stage[TS + (j0 + q * TS - hb)] = h[q];
+            if (g[q] >= 0) {
+                vec2_t<T> h;
+                h.x = hx[q];
+                h.y = hy[q];
+                stage[TS + (j0 + q * TS - hb)] = h;
+            }
     }
     __syncthreads();
     T ax = T(0), ay = T(0);

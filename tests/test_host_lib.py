@@ -251,3 +251,21 @@ def test_oversized_triangle_count_is_rejected_before_allocating():
     h = ctypes.c_void_p()
     tri = np.zeros(3, dtype=np.int32)
     assert lib.lms_build_csr(3, (1 << 40) + 1, lms._np_ptr(tri), None, ctypes.byref(h)) == 1
+
+
+def test_no_kernel_spills_to_scratch():
+    # every device kernel must keep its arrays in registers: a kernel with
+    # private (scratch) memory runs its loads through memory and slows down
+    import subprocess
+    from paper_1606_00803_amd import build as b
+    src = os.path.join(b.CSRC, "lms_device.hip")
+    cmd = [b._hipcc(), *b.COMMON, f"--offload-arch={b.ARCH}", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-Wno-unused-command-line-argument", "-Rpass-analysis=kernel-resource-usage",
+           "--cuda-device-only", "-c", src, "-o", os.devnull]
+    out = subprocess.run(cmd, capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr[-2000:]
+    names = re.findall(r"Function Name: (\S+)", out.stderr)
+    scratch = [int(v) for v in re.findall(r"ScratchSize \[bytes/lane\]: (\d+)", out.stderr)]
+    assert len(names) == len(scratch) and len(names) > 50
+    spilled = [n for n, sc in zip(names, scratch) if sc > 0]
+    assert not spilled, spilled
