@@ -117,6 +117,19 @@ def stream_copy_gbs(torch, mbytes=2048):
     return 2 * n * 8 * reps / (t.ms * 1e-3) / 1e9
 
 
+def calibration_copy(torch, mb):
+    """A device copy of known size (mb MiB), for scaling the memory counters;
+    a 1 GiB fill in between evicts the source from the caches first."""
+    if not mb:
+        return
+    a = torch.empty(mb << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(0.0)
+    del flush
+    torch.empty_like(a).copy_(a)
+    torch.cuda.synchronize()
+    del a
+
+
 def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
     """Reorder, upload, time `steps` calls of `sweeps` sweeps.  Returns a dict."""
     from paper_1606_00803_amd import lms  # noqa: F401
@@ -202,15 +215,7 @@ def bench_ocean(torch, args):
     info = M.info()
     log(f"ocean mesh n={info['n']} n_free={info['n_free']} T={m.T} nnz={info['nnz']} "
         f"colours={info['n_colors']} gen={t_gen:.2f}s csr={t_csr:.2f}s")
-    if args.calibration_copy_mb:
-        # a device copy of known size, for scaling the memory counters; a 1 GiB
-        # fill in between evicts the source from the caches first
-        a = torch.empty(args.calibration_copy_mb << 17, dtype=torch.float64, device="cuda").fill_(1.0)
-        flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(0.0)
-        del flush
-        torch.empty_like(a).copy_(a)
-        torch.cuda.synchronize()
-        del a
+    calibration_copy(torch, args.calibration_copy_mb)
     results, reorder_s = {}, {}
     for kind in [o for o in args.orderings.split(",") if o]:
         t0 = time.perf_counter()
@@ -281,6 +286,7 @@ def bench_graded16m(torch, args):
     M = lms.Mesh.build_csr(m.n, m.tri)
     info = M.info()
     log(f"graded mesh n={info['n']} n_free={info['n_free']} T={m.T} nnz={info['nnz']} gen={t_gen:.1f}s")
+    calibration_copy(torch, args.calibration_copy_mb)
     results, reorder_s, finals = {}, {}, {}
     for kind in [o for o in args.orderings.split(",") if o in ("rdr", "ori", "bfs", "random")]:
         t0 = time.perf_counter()
