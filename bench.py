@@ -37,7 +37,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 ORDER_NAMES = ["ori", "bfs", "rdr", "random"]
 RANDOM_SEED = 1002
 METRIC = "vertex-updates/sec and % HBM roofline per ordering (ORI/BFS/RDR/random), FP64 vs FP32"
-COUNTERS_MD = os.path.join(ROOT, "profiles", "sweep_ocean_rdr_f64_counters.md")
+COUNTERS = {"ocean": os.path.join(ROOT, "profiles", "sweep_ocean_rdr_f64_counters.md"),
+            "graded16m": os.path.join(ROOT, "profiles", "sweep_graded16m_counters.md")}
 DEVICE_SRC = os.path.join(ROOT, "paper_1606_00803_amd", "csrc", "lms_device.hip")
 
 
@@ -62,19 +63,19 @@ def device_source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def counters_traffic(kernel_name):
-    """HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the
+def counters_traffic(kernel_name, prec, path):
+    """HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from a
     committed counter summary, when it was taken on the current kernel source;
-    the summary lists every sweep variant the autotuner timed."""
+    the summary lists every sweep variant the autotuner timed, per precision."""
     try:
-        text = open(COUNTERS_MD).read()
+        text = open(path).read()
     except OSError:
         return None
     src = re.search(r"^- source_sha256: (\S+)$", text, flags=re.M)
     if not src or src.group(1) != device_source_hash():
         return None
-    for name, traffic in re.findall(r"^\| `(\S+)` \|[^|]*\|[^|]*\| (\d+) \|", text, flags=re.M):
-        if name == kernel_name:
+    for name, p, traffic in re.findall(r"^\| `(\S+)` \| (f64|f32) \|[^|]*\| (\d+) \|", text, flags=re.M):
+        if name == kernel_name and p == prec:
             return float(traffic)
     return None
 
@@ -192,8 +193,8 @@ def result_line(value, steps, warmup, ms_per_step, dtype, config, roofline, cpu,
     return out
 
 
-def roofline_of(r):
-    traffic = counters_traffic(r["sweep_kernel"])
+def roofline_of(r, prec="f64", workload="ocean"):
+    traffic = counters_traffic(r["sweep_kernel"], prec, COUNTERS[workload]) if workload in COUNTERS else None
     return {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "sweep " + r["sweep_kernel"], "bytes_per_launch": r["bytes_per_sweep"],
@@ -269,7 +270,7 @@ def bench_ocean(torch, args):
                      f"{SWEEPS} Jacobi sweeps per step, RDR ordering, float64",
          "n": info["n"], "n_free": info["n_free"], "n_tri": m.T, "nnz": info["nnz"],
          "sweeps_per_step": SWEEPS, "mesh_sha256": meshgen.mesh_hash(m)},
-        roofline_of(h), cpu, per_ordering=strip(results), extras=extras)
+        roofline_of(h, "f64", "ocean"), cpu, per_ordering=strip(results), extras=extras)
 
 
 def strip(results):
@@ -342,7 +343,7 @@ def bench_graded16m(torch, args):
         {"workload": f"graded mesh refined 4x toward a seeded curve: {SWEEPS} Jacobi sweeps per step, "
                      "RDR ordering, float32 storage and accumulation",
          "n": info["n"], "n_free": info["n_free"], "n_tri": m.T, "nnz": info["nnz"], "sweeps_per_step": SWEEPS},
-        roofline_of(h), cpu, per_ordering=strip(results), extras=extras)
+        roofline_of(h, "f32", "graded16m"), cpu, per_ordering=strip(results), extras=extras)
 
 
 def bench_batch512(torch, args):
@@ -370,7 +371,7 @@ def bench_batch512(torch, args):
         {"workload": f"batch of {len(ms)} jittered grids, sizes log-uniform 1k-200k vertices, "
                      f"{SWEEPS} sweeps each in one launch per sweep, RDR per mesh, float64",
          "n": info["n"], "n_mesh": len(ms), "sweeps_per_step": SWEEPS},
-        roofline_of(h), None, per_ordering=strip(results))
+        roofline_of(h, "f64", "batch512"), None, per_ordering=strip(results))
 
 
 def bench_graded64m(torch, args):
