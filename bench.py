@@ -365,13 +365,31 @@ def bench_batch512(torch, args):
             results[f"{kind}_{prec}"] = r
             log(f"{kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  sweep "
                 f"{r['sweep_us_events']:8.2f} us  {r['achieved_gbs']:8.1f} GB/s  [{r['sweep_kernel']}]")
+    # a batch of small meshes (every one fits in LDS): all sweeps in one launch,
+    # against the per-sweep path
+    small = meshgen.batch(count=8192, seed=44, n_min=256, n_max=2000)
+    su, sv, st_ = meshgen.concat(small)
+    SB = lms.Mesh.build_csr_batched(sv, st_, np.concatenate([mm.tri for mm in small]))
+    SB.reorder("rdr", x0=su.x, y0=su.y)
+    extras = {}
+    for flag, label in (("1", "one_launch"), ("0", "per_sweep")):
+        os.environ["LMS_SMALL_BATCH"] = flag
+        try:
+            for prec in ("f64", "f32"):
+                r, _ = run_fixed(torch, SB, su, "rdr", prec, SWEEPS, args.steps, args.warmup)
+                extras[f"small_batch_{label}_{prec}"] = dict(vertex_updates_per_s=r["vertex_updates_per_s"],
+                                                             ms_per_step=r["ms_per_step"])
+                log(f"small batch ({len(small)} meshes, n={su.n}) {label:10s} {prec}: "
+                    f"{r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s")
+        finally:
+            os.environ.pop("LMS_SMALL_BATCH", None)
     h = results["rdr_f64"]
     return result_line(
         h["vertex_updates_per_s"], args.steps, args.warmup, h["ms_per_step"], "f64",
         {"workload": f"batch of {len(ms)} jittered grids, sizes log-uniform 1k-200k vertices, "
                      f"{SWEEPS} sweeps each in one launch per sweep, RDR per mesh, float64",
          "n": info["n"], "n_mesh": len(ms), "sweeps_per_step": SWEEPS},
-        roofline_of(h, "f64", "batch512"), None, per_ordering=strip(results))
+        roofline_of(h, "f64", "batch512"), None, per_ordering=strip(results), extras=extras)
 
 
 def bench_graded64m(torch, args):

@@ -558,6 +558,82 @@ __global__ __launch_bounds__(TS) void k_jacobi_halo(const int32_t *__restrict__ 
     }
 }
 
+// All K Jacobi sweeps of a batch of small meshes in one launch, one workgroup
+// of 256 threads per mesh (Algorithm 1 per mesh).  A mesh's padded index is
+// read once, turned into 16-bit slots local to the mesh (two per register)
+// and kept in registers for every sweep; its coordinates sit in one LDS copy.
+// Each sweep computes its rows' new positions into registers, waits for the
+// whole workgroup, stores them and waits again, so no row reads a value of
+// the sweep it is in.  Thread t owns rows t, t+256, ..., R rows at most.
+// Same order of additions and the same divide as every other sweep kernel.
+template <typename T, int W, int R>
+__global__ __launch_bounds__(256) void k_small_meshes(const int64_t *__restrict__ v_off,
+                                                      const int32_t *__restrict__ ell,
+                                                      vec2_t<T> *__restrict__ a, vec2_t<T> *__restrict__ b,
+                                                      int32_t K) {
+    static_assert(W % 2 == 0, "slots are packed in pairs");
+    extern __shared__ unsigned char lds_raw[];
+    vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
+    const int64_t vb = v_off[blockIdx.x];
+    const int32_t nv = int32_t(v_off[blockIdx.x + 1] - vb);
+    uint32_t slot[R][W / 2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t i = int32_t(threadIdx.x) + 256 * r;
+#pragma unroll
+        for (int q = 0; q < W / 2; ++q) slot[r][q] = 0xFFFFFFFFu;
+        if (i < nv) {
+            int32_t u[W];
+            load_row_ids<W>(ell + (vb + i) * W, u);
+#pragma unroll
+            for (int q = 0; q < W / 2; ++q) {
+                const uint32_t lo = u[2 * q] >= 0 ? uint32_t(u[2 * q] - vb) : 0xFFFFu;
+                const uint32_t hi = u[2 * q + 1] >= 0 ? uint32_t(u[2 * q + 1] - vb) : 0xFFFFu;
+                slot[r][q] = lo | (hi << 16);
+            }
+            sp[i] = a[vb + i];
+        }
+    }
+    __syncthreads();
+    for (int32_t k = 0; k < K; ++k) {
+        vec2_t<T> o[R];
+        bool w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            w[r] = false;
+            if (256 * r >= nv) continue;  // the same for the whole workgroup
+            T ax = T(0), ay = T(0);
+            int c = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const uint32_t id = (slot[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
+                if (id != 0xFFFFu) {
+                    const vec2_t<T> p = sp[id];
+                    ax += p.x;
+                    ay += p.y;
+                    ++c;
+                }
+            }
+            w[r] = c > 0;
+            o[r].x = w[r] ? ax / T(c) : T(0);
+            o[r].y = w[r] ? ay / T(c) : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (256 * r < nv && w[r]) sp[int32_t(threadIdx.x) + 256 * r] = o[r];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t i = int32_t(threadIdx.x) + 256 * r;
+        if (i < nv) {
+            a[vb + i] = sp[i];
+            b[vb + i] = sp[i];
+        }
+    }
+}
+
 // Multicolour sweep of one colour on the interleaved copy, in place.  The
 // colour's vertices read their neighbours' current positions (none of which
 // has this colour) through the colour-major padded index: entry k of the
@@ -878,6 +954,7 @@ struct DeviceState {
     double *tw = nullptr;
     int32_t *trec = nullptr;
     int64_t *t_off = nullptr, *v_off = nullptr;
+    int64_t *v_cur = nullptr;    // per-mesh vertex offsets in the current labels
     // scratch, kept across versions
     double *partials = nullptr;
     int nparts = 0;
@@ -970,6 +1047,7 @@ DeviceState &ensure_device(Mesh &M) {
         d->vt = upload(d, M.vt);
         d->t_off = upload(d, M.t_off);
         d->v_off = upload(d, M.v_off);
+        d->v_cur = upload(d, M.v_off);  // orderings stay within each mesh's range
         void *qm = nullptr;
         HIP_CHECK(hipMalloc(&qm, sizeof(double) * size_t(M.n_mesh)));
         d->arrays.push_back(qm);
@@ -1522,6 +1600,55 @@ bool overlaps(const void *a, const void *b, size_t bytes) {
     return pa < pb + bytes && pb < pa + bytes;
 }
 
+// Rows per thread the one-launch small-mesh path needs for this batched
+// handle (its largest mesh over 256 threads, rounded up to 1, 2, 4, 8 or 16),
+// or 0 when the path does not apply: not a batch, no padded index, a mesh
+// above 4096 vertices (16-bit slots, the registers and one LDS copy of at most
+// 64 KB), or LMS_SMALL_BATCH=0.
+int small_batch_rows(const Mesh &M) {
+    if (M.n_mesh < 2 || (M.ell_w != 8 && M.ell_w != 12 && M.ell_w != 16)) return 0;
+    if (!env_flag("LMS_SMALL_BATCH", true)) return 0;
+    int64_t largest = 0;
+    for (int32_t i = 0; i < M.n_mesh; ++i) largest = std::max<int64_t>(largest, M.v_off[i + 1] - M.v_off[i]);
+    for (int r = 1; r <= 16; r *= 2)
+        if (largest <= 256 * r) return r;
+    return 0;
+}
+
+template <typename T>
+void launch_small_meshes(DeviceState &d, const Mesh &M, vec2_t<T> *A, vec2_t<T> *B, int32_t K, int rows,
+                         hipStream_t s) {
+    int64_t largest = 0;
+    for (int32_t i = 0; i < M.n_mesh; ++i) largest = std::max<int64_t>(largest, M.v_off[i + 1] - M.v_off[i]);
+    if (rows < 1 || rows > 16 || largest > 256 * int64_t(rows)) fail(LMS_ERR_STATE, "small-mesh rows do not fit");
+    const size_t lds = size_t(largest) * sizeof(vec2_t<T>);
+    auto go = [&](auto kern) { kern<<<M.n_mesh, 256, lds, s>>>(d.v_cur, d.ell, A, B, K); };
+#define LMS_SMALL_R(W)                          \
+    switch (rows) {                             \
+        case 1: go(k_small_meshes<T, W, 1>); break;   \
+        case 2: go(k_small_meshes<T, W, 2>); break;   \
+        case 4: go(k_small_meshes<T, W, 4>); break;   \
+        case 8: go(k_small_meshes<T, W, 8>); break;   \
+        case 16: go(k_small_meshes<T, W, 16>); break; \
+        default: fail(LMS_ERR_STATE, "small-mesh rows per thread");   \
+    }
+    switch (M.ell_w) {
+        case 8:
+            LMS_SMALL_R(8)
+            break;
+        case 12:
+            LMS_SMALL_R(12)
+            break;
+        case 16:
+            LMS_SMALL_R(16)
+            break;
+        default:
+            fail(LMS_ERR_STATE, "no padded index for the small-mesh path");
+    }
+#undef LMS_SMALL_R
+    launch_check();
+}
+
 // lms_smooth on the interleaved working copies: pack P_0 into both copies,
 // sweep back and forth between them (graph-captured), unpack the last one.
 template <typename T>
@@ -1538,7 +1665,15 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     const std::string base = std::string("packed|") + (p == LMS_FP64 ? "f64" : "f32") + "|" + ptr_key(A) + "|" +
                              ptr_key(B) + "|cfg" + std::to_string(cfg) + "|" + std::to_string(int(sch));
     int32_t iters = 0;
-    if (!o.check_quality) {
+    const int small_rows = colour || o.check_quality ? 0 : small_batch_rows(M);
+    if (small_rows > 0) {
+        // every mesh of the batch fits in LDS: all K sweeps in one launch
+        const int32_t K = o.max_iters;
+        if (K > 0) launch_small_meshes<T>(d, M, A, B, K, small_rows, s);
+        iters = K;
+        r.stopped_by = LMS_STOP_MAX_ITERS;
+        r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
+    } else if (!o.check_quality) {
         const int32_t K = o.max_iters;
         if (K > 0)
             run_maybe_graph(d, "fixed|" + base + "|" + std::to_string(K), s, [&](hipStream_t cs) {
@@ -1596,6 +1731,10 @@ template <typename T>
 void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precision p, lms_scheme sch,
                   const lms_smooth_opts &o, hipStream_t s, lms_smooth_result &r) {
     if (sch == LMS_JACOBI) {
+        if (!o.check_quality && small_batch_rows(M) > 0) {
+            smooth_packed<T>(M, d, x, y, p, sch, o, s, r);
+            return;
+        }
         tune_sweep<T>(d, M, x, y, tx, ty, s);
         if (sweep_config_packed(d.smooth_cfg[sizeof(T) == 8 ? 0 : 1])) {
             smooth_packed<T>(M, d, x, y, p, sch, o, s, r);

@@ -445,3 +445,37 @@ def test_quality_when_a_vertex_has_many_triangles():
         Q = M.quality(x, y, q_vertex=qv)
         assert abs(Q - oq.global_quality(m.x, m.y, m.tri, m.n)) <= 1e-12
         assert np.max(np.abs(qv.cpu().numpy() - oq.vertex_quality(m.x, m.y, m.tri, m.n))) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("K,sizes", [(7, (60, 1500)), (30, (60, 1500)), (11, (3000, 4096))])
+def test_small_mesh_batch_in_one_launch(prec, K, sizes):
+    # every mesh fits in LDS: all K sweeps run in one launch, one workgroup per
+    # mesh (up to 16 rows per thread at 4096 vertices); same bits as the
+    # per-sweep path, and the oracle per mesh
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    dt = torch.float64 if prec == "f64" else torch.float32
+    count = 150 if sizes[1] < 2000 else 40
+    ms = meshgen.batch(count=count, seed=9, n_min=sizes[0], n_max=sizes[1])
+    assert max(m.n for m in ms) <= 4096
+    u, v_off, t_off = meshgen.concat(ms)
+    local = np.concatenate([m.tri for m in ms])
+    outs = []
+    for flag in ("1", "0"):
+        os.environ["LMS_SMALL_BATCH"] = flag
+        try:
+            B = lms.Mesh.build_csr_batched(v_off, t_off, local)
+            x, y, r, _ = run_library(u, "rdr", K, dtype=dt, M=B)
+        finally:
+            os.environ.pop("LMS_SMALL_BATCH", None)
+        assert r["iters"] == K
+        outs.append((x, y))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    if prec == "f64":
+        for i in (0, 7, count // 2, count - 1):
+            m = ms[i]
+            ex, ey = osm.jacobi(oracle_topology(m), m.x, m.y, K)
+            seg = slice(v_off[i], v_off[i + 1])
+            assert np.max(np.abs(outs[0][0][seg] - ex)) <= TOL64 * extent(m.xy)
+            assert np.max(np.abs(outs[0][1][seg] - ey)) <= TOL64 * extent(m.xy)
