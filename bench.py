@@ -193,12 +193,21 @@ def result_line(value, steps, warmup, ms_per_step, dtype, config, roofline, cpu,
     return out
 
 
+def sweeps_per_launch(kernel_name):
+    """A temporally blocked variant ("tb/.../k2/...") runs k sweeps per launch."""
+    m = re.search(r"^tb/.*?/k(\d+)/", kernel_name)
+    return int(m.group(1)) if m else 1
+
+
 def roofline_of(r, prec="f64", workload="ocean"):
+    # one launch processes k sweeps' worth of vertex updates: its algorithmic
+    # bytes are k x B_sweep, over a launch that lasts k x the time per sweep
+    k = sweeps_per_launch(r["sweep_kernel"])
     traffic = counters_traffic(r["sweep_kernel"], prec, COUNTERS[workload]) if workload in COUNTERS else None
     return {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "sweep " + r["sweep_kernel"], "bytes_per_launch": r["bytes_per_sweep"],
-            "avg_launch_us": r["sweep_us_events"]}
+            "kernel": "sweep " + r["sweep_kernel"], "sweeps_per_launch": k,
+            "bytes_per_launch": k * r["bytes_per_sweep"], "avg_launch_us": k * r["sweep_us_events"]}
 
 
 # ---------------------------------------------------------------- workloads

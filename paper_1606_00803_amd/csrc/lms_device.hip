@@ -558,6 +558,142 @@ __global__ __launch_bounds__(TS) void k_jacobi_halo(const int32_t *__restrict__ 
     }
 }
 
+// The padded slots of one row, two 16-bit slots per word (slot 2q in the
+// low half of word q).
+template <int W>
+__device__ __forceinline__ void load_slot_words(const uint16_t *__restrict__ row, uint32_t (&w)[W / 2]) {
+    if constexpr (W % 8 == 0) {
+#pragma unroll
+        for (int q = 0; q < W / 8; ++q) {
+            const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row) + q);
+            w[4 * q] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+    } else {
+        static_assert(W % 4 == 0, "padded width must be a multiple of 4");
+#pragma unroll
+        for (int q = 0; q < W / 4; ++q) {
+            const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(row) + q);
+            w[2 * q] = v.x;
+            w[2 * q + 1] = v.y;
+        }
+    }
+}
+
+// Temporally blocked Jacobi: k sweeps (Eq. 1, Algorithm 1) of the tile's
+// own rows in one pass over memory.  Tile t (rows tile_ptr[t] ..
+// tile_ptr[t+1]-1) stages its own rows and k halo
+// rings of src in LDS (local slots in ring order).  Sweep j of the pass
+// updates, in LDS, every row of the tile's own set and of rings 1..k-j: a
+// row of ring m reads only rings up to m+1, which still hold values of the
+// previous sweep.  So after k sweeps the own rows hold exactly what k
+// separate sweeps give them; halo rows are computed redundantly, in the same
+// order, with the same bits.  Each sweep computes into registers, waits,
+// stores, waits; the last one writes the own free rows to dst.  Thread t
+// owns local rows t, t+BS, ..., R of them; the plan guarantees that the
+// rows updated by the first sweep fit (ring[k-1] <= BS*R) and that the
+// staging area fits the dynamic LDS it is launched with.
+template <typename T, int BS, int W, int R, int MAP>
+__global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ tile_ptr,
+                                                  const int32_t *__restrict__ ring, int32_t kp, int32_t k,
+                                                  const int64_t *__restrict__ halo_ptr,
+                                                  const int32_t *__restrict__ halo,
+                                                  const int64_t *__restrict__ lidx_ptr,
+                                                  const uint16_t *__restrict__ lidx,
+                                                  const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst) {
+    static_assert(W % 4 == 0, "padded width must be a multiple of 4");
+    extern __shared__ unsigned char lds_raw[];
+    vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
+    const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
+    const int tid = int(threadIdx.x);
+    const int32_t b = tile_ptr[tile];
+    const int32_t *rc = ring + int64_t(tile) * (kp + 1);
+    const int32_t nown = rc[0], nload = rc[k], nupd = rc[k - 1];
+    const int64_t hb = halo_ptr[tile], lb = lidx_ptr[tile];
+    uint32_t wd[R][W / 2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t i = tid + BS * r;
+        if (i < nupd) {
+            load_slot_words<W>(lidx + (lb + i) * W, wd[r]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < W / 2; ++q) wd[r][q] = 0xFFFFFFFFu;
+        }
+    }
+    for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
+    const int32_t nh = nload - nown;
+    for (int32_t j0 = tid; j0 < nh; j0 += 4 * BS) {
+        int32_t g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = j0 + q * BS < nh ? halo[hb + j0 + q * BS] : -1;
+        T hx[4], hy[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            hx[q] = T(0);
+            hy[q] = T(0);
+            if (g[q] >= 0) {
+                const vec2_t<T> h = src[g[q]];
+                hx[q] = h.x;
+                hy[q] = h.y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (g[q] >= 0) {
+                vec2_t<T> h;
+                h.x = hx[q];
+                h.y = hy[q];
+                sp[nown + j0 + q * BS] = h;
+            }
+    }
+    __syncthreads();
+    for (int32_t j = 1; j <= k; ++j) {
+        const int32_t m = rc[k - j];  // rows updated by this sweep
+        vec2_t<T> o[R];
+        bool w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            w[r] = false;
+            o[r].x = T(0);
+            o[r].y = T(0);
+            const int32_t i = tid + BS * r;
+            if (BS * r >= m) continue;  // the same for the whole workgroup
+            if (i >= m) continue;
+            T ax = T(0), ay = T(0);
+            int c = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const uint32_t id = (wd[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
+                if (id != 0xFFFFu) {
+                    const vec2_t<T> p = sp[id];
+                    ax += p.x;
+                    ay += p.y;
+                    ++c;
+                }
+            }
+            w[r] = c > 0;
+            if (c > 0) {
+                o[r].x = ax / T(c);
+                o[r].y = ay / T(c);
+            }
+        }
+        if (j == k) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (w[r]) dst[b + tid + BS * r] = o[r];
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (w[r]) sp[tid + BS * r] = o[r];
+            __syncthreads();
+        }
+    }
+}
+
 // All K Jacobi sweeps of a batch of small meshes in one launch, one workgroup
 // of 256 threads per mesh (Algorithm 1 per mesh).  A mesh's padded index is
 // read once, turned into 16-bit slots local to the mesh (two per register)
@@ -942,7 +1078,7 @@ struct DeviceState {
     uint64_t version = ~uint64_t(0);
     std::vector<void *> arrays;  // mesh arrays of the current version
     int32_t *row_ptr = nullptr, *col = nullptr, *color_list = nullptr, *new2old = nullptr;
-    int32_t *ell = nullptr;  // padded adjacency (column-major), when the handle has one
+    int32_t *ell = nullptr;  // padded adjacency (row-major), when the handle has one
     int32_t *color_ell = nullptr;  // colour-major padded adjacency
     struct HaloDev {
         int32_t ts = 0, h_max = 0;
@@ -950,6 +1086,14 @@ struct DeviceState {
         uint16_t *lidx = nullptr;
     };
     std::vector<HaloDev> halos;  // uploaded tile plans of the current version
+    struct TBDev {
+        int32_t ts = 0, k = 0, u_cap = 0, l_cap = 0, tiles = 0, l_max = 0, u_max = 0;
+        bool fits = false;
+        int32_t *tile_ptr = nullptr, *ring = nullptr, *halo = nullptr;
+        int64_t *halo_ptr = nullptr, *lidx_ptr = nullptr;
+        uint16_t *lidx = nullptr;
+    };
+    std::vector<TBDev> tbs;      // uploaded temporal-blocking plans of the current version
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
     double *tw = nullptr;
     int32_t *trec = nullptr;
@@ -971,6 +1115,7 @@ struct DeviceState {
     bool use_graphs = true;
     int sweep_cfg[2] = {-1, -1};     // separate-array sweep variant per precision, -1 = not tuned
     int smooth_cfg[2] = {-1, -1};    // variant lms_smooth uses (may sweep the interleaved copy)
+    int tb_cfg[2] = {-1, -1};        // temporally blocked variant for fixed-K Jacobi, -1 = none
     void *pk[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [precision][ping|pong] interleaved copies
     size_t pk_n[2] = {0, 0};
     float tune_us[2][64] = {};       // measured time per variant (microseconds per sweep)
@@ -1031,6 +1176,7 @@ DeviceState &ensure_device(Mesh &M) {
         free_graphs(d);
         free_arrays(d);
         d->halos.clear();  // their arrays were in d->arrays
+        d->tbs.clear();
         d->version = ~uint64_t(0);
         d->row_ptr = upload(d, M.row_ptr);
         d->col = upload(d, M.col);
@@ -1054,6 +1200,7 @@ DeviceState &ensure_device(Mesh &M) {
         d->qmesh = static_cast<double *>(qm);
         d->sweep_cfg[0] = d->sweep_cfg[1] = -1;  // a new ordering is tuned afresh
         d->smooth_cfg[0] = d->smooth_cfg[1] = -1;
+        d->tb_cfg[0] = d->tb_cfg[1] = -1;
         d->version = M.version;
     }
     return *d;
@@ -1131,12 +1278,60 @@ void launch_check() {
 constexpr int kNumSweepConfigs = 44;
 constexpr int kDefaultSweepConfig = 0;
 
+// Temporally blocked variants, k sweeps per pass over memory:
+// TB(id, block size, padded width, rows per thread, MAP, tile size, k).
+// TB(id, block size, padded width, rows per thread, MAP, nominal tile size,
+//    k, staging cap in rows).  A tile whose first sweep would update more
+// than block size x rows per thread rows, or whose staging area would pass
+// the cap, is halved until it fits.
+#define LMS_TB_CONFIGS(TB)                 \
+    TB(44, 128, 8, 4, 0, 128, 2, 1024)     \
+    TB(45, 256, 8, 2, 0, 256, 2, 1024)     \
+    TB(46, 256, 8, 4, 0, 256, 2, 2048)     \
+    TB(47, 256, 8, 4, 0, 512, 2, 2048)     \
+    TB(48, 256, 8, 4, 0, 256, 3, 2048)     \
+    TB(49, 256, 8, 8, 0, 512, 3, 4096)     \
+    TB(50, 256, 8, 8, 0, 1024, 2, 4096)    \
+    TB(51, 512, 8, 8, 0, 512, 4, 4096)     \
+    TB(52, 256, 12, 4, 0, 512, 2, 2048)    \
+    TB(53, 256, 12, 8, 0, 1024, 2, 4096)   \
+    TB(54, 256, 12, 4, 0, 256, 3, 2048)    \
+    TB(55, 256, 16, 4, 0, 512, 2, 2048)
+constexpr int kFirstTBConfig = kNumSweepConfigs;
+constexpr int kNumAllConfigs = 56;
+
+struct TBShape {
+    int bs = 0, w = 0, r = 0, map = 0, ts = 0, k = 0, lcap = 0;
+};
+
+bool is_tb_config(int cfg) { return cfg >= kFirstTBConfig && cfg < kNumAllConfigs; }
+
+TBShape tb_shape(int cfg) {
+    switch (cfg) {
+#define TB(id, bs, w, r, map, ts, k, lcap) \
+    case id:                               \
+        return TBShape{bs, w, r, map, ts, k, lcap};
+        LMS_TB_CONFIGS(TB)
+#undef TB
+    }
+    return TBShape{};
+}
+
+// Sweeps one launch of variant cfg performs.
+int sweep_config_depth(int cfg) { return is_tb_config(cfg) ? tb_shape(cfg).k : 1; }
+
 std::string map_name(int map) {
     return map == 0 ? "linear" : (map < 0 ? "xcd" : "xcd" + std::to_string(map));
 }
 
 std::string sweep_config_name(int cfg) {
     char buf[96];
+    if (is_tb_config(cfg)) {
+        const TBShape t = tb_shape(cfg);
+        std::snprintf(buf, sizeof(buf), "tb/ts%d/k%d/bs%d/w%d/r%d/l%d/%s", t.ts, t.k, t.bs, t.w, t.r, t.lcap,
+                      map_name(t.map).c_str());
+        return buf;
+    }
     switch (cfg) {
 #define ROW(id, bs, u, r, map, nt)                                                              \
     case id:                                                                                    \
@@ -1176,6 +1371,7 @@ std::string sweep_config_name(int cfg) {
 
 // Padded width an ELL variant needs (0: not a padded-index variant).
 int sweep_config_ell_width(int cfg) {
+    if (is_tb_config(cfg)) return tb_shape(cfg).w;
     switch (cfg) {
 #define ROW(id, bs, u, r, map, nt) \
     case id:                       \
@@ -1208,6 +1404,7 @@ int sweep_config_ell_width(int cfg) {
 
 // Variants that sweep the interleaved (x, y) working copy.
 bool sweep_config_packed(int cfg) {
+    if (is_tb_config(cfg)) return true;
     switch (cfg) {
 #define ROW(id, bs, u, r, map, nt) \
     case id:                       \
@@ -1287,13 +1484,47 @@ const DeviceState::HaloDev &ensure_halo(DeviceState &d, Mesh &M, int32_t ts) {
     return d.halos.back();
 }
 
+const DeviceState::TBDev *find_tb(const DeviceState &d, const TBShape &t) {
+    for (const auto &h : d.tbs)
+        if (h.ts == t.ts && h.k == t.k && h.u_cap == t.bs * t.r && h.l_cap == t.lcap) return &h;
+    return nullptr;
+}
+
+// Build (host) and upload the temporal-blocking plan of variant shape t.
+const DeviceState::TBDev &ensure_tb(DeviceState &d, Mesh &M, const TBShape &t) {
+    if (const DeviceState::TBDev *h = find_tb(d, t)) return *h;
+    const Mesh::TBPlan &P = tb_plan(M, t.ts, t.k, t.bs * t.r, t.lcap);
+    DeviceState::TBDev h;
+    h.ts = t.ts;
+    h.k = t.k;
+    h.u_cap = t.bs * t.r;
+    h.l_cap = t.lcap;
+    h.fits = P.fits;
+    h.tiles = P.tiles;
+    h.l_max = P.l_max;
+    h.u_max = P.u_max;
+    h.tile_ptr = upload(&d, P.tile_ptr);
+    h.ring = upload(&d, P.ring);
+    h.halo_ptr = upload(&d, P.halo_ptr);
+    h.halo = upload(&d, P.halo);
+    h.lidx_ptr = upload(&d, P.lidx_ptr);
+    h.lidx = upload(&d, P.lidx);
+    d.tbs.push_back(h);
+    return d.tbs.back();
+}
+
 int sweep_config_tile(int cfg);  // tile size of a halo-staged variant, 0 otherwise
 
 // Whether variant cfg can run on this mesh in precision T (builds the tile
-// plan of a halo-staged variant on first use).
+// plan of a halo-staged or temporally blocked variant on first use).
 template <typename T>
 bool sweep_config_usable(int cfg, DeviceState &d, Mesh &M) {
     if (!sweep_config_eligible(cfg, M)) return false;
+    if (is_tb_config(cfg)) {
+        if (!env_flag("LMS_TEMPORAL_BLOCKING", true) || M.n == 0) return false;
+        const DeviceState::TBDev &h = ensure_tb(d, M, tb_shape(cfg));
+        return h.fits && size_t(h.l_max) * sizeof(vec2_t<T>) <= size_t(64) * 1024;
+    }
     const int ts = sweep_config_tile(cfg);
     if (ts == 0) return true;
     const DeviceState::HaloDev &h = ensure_halo(d, M, ts);
@@ -1334,10 +1565,41 @@ void launch_sweep_cfg(int cfg, const DeviceState &d, const Mesh &M, const T *sx,
     }
 }
 
+// k (1 <= k <= the variant's depth) Jacobi sweeps src -> dst in one pass of
+// a temporally blocked variant.  dst's fixed rows are not written.
+template <typename T>
+void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst, int32_t k,
+                   hipStream_t s) {
+    const TBShape t = tb_shape(cfg);
+    const DeviceState::TBDev *h = find_tb(d, t);
+    if (!h || !h->fits || M.ell_w != t.w) fail(LMS_ERR_STATE, "temporally blocked variant launched without its plan");
+    if (k < 1 || k > t.k) fail(LMS_ERR_STATE, "temporally blocked pass deeper than its plan");
+    if (h->u_max > t.bs * t.r || size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024)
+        fail(LMS_ERR_STATE, "temporally blocked plan does not fit the variant");
+    if (h->tiles == 0) return;
+    const size_t lds = size_t(h->l_max) * sizeof(vec2_t<T>);
+    switch (cfg) {
+#define TB(id, bs, w, r, map, ts, kk, lcap)                                                                    \
+    case id:                                                                                                   \
+        k_jacobi_tb<T, bs, w, r, map><<<h->tiles, bs, lds, s>>>(h->tile_ptr, h->ring, t.k, k, h->halo_ptr,     \
+                                                                 h->halo, h->lidx_ptr, h->lidx, src, dst);      \
+        break;
+        LMS_TB_CONFIGS(TB)
+#undef TB
+        default:
+            fail(LMS_ERR_STATE, "not a temporally blocked variant");
+    }
+}
+
 template <typename T>
 void launch_sweep2_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst,
                        const StopState *st, hipStream_t s) {
     const int64_t n = M.n;
+    if (is_tb_config(cfg)) {
+        if (st) fail(LMS_ERR_STATE, "temporally blocked variants do not run under the stopping rule");
+        launch_tb_cfg<T>(cfg, d, M, src, dst, 1, s);
+        return;
+    }
     switch (cfg) {
 #define ROW(id, bs, u, r, map, nt)
 #define LDS(id, bs, cap, map)
@@ -1403,12 +1665,14 @@ template <typename T>
 void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy, hipStream_t s) {
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (d.sweep_cfg[pi] >= 0) return;
+    d.tb_cfg[pi] = -1;
     if (const char *f = std::getenv("LMS_SWEEP_CONFIG")) {
         const int c = std::atoi(f);
-        if (c < 0 || c >= kNumSweepConfigs) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG out of range");
+        if (c < 0 || c >= kNumAllConfigs) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG out of range");
         if (!sweep_config_usable<T>(c, d, M)) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG names a variant this mesh cannot use");
         d.sweep_cfg[pi] = sweep_config_packed(c) ? kDefaultSweepConfig : c;
-        d.smooth_cfg[pi] = c;
+        d.smooth_cfg[pi] = is_tb_config(c) ? kDefaultSweepConfig : c;
+        if (is_tb_config(c)) d.tb_cfg[pi] = c;
         return;
     }
     if (!env_flag("LMS_AUTOTUNE", true)) {
@@ -1424,11 +1688,11 @@ void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
     }
     const int64_t work = int64_t(M.n) + int64_t(M.col.size());
     const int reps = work > (int64_t(1) << 26) ? 3 : (work > (int64_t(1) << 22) ? 6 : 12);
-    int best = kDefaultSweepConfig, best_all = kDefaultSweepConfig;
-    float best_ms = 3.0e38f, best_all_ms = 3.0e38f;
+    int best = kDefaultSweepConfig, best_all = kDefaultSweepConfig, best_tb = -1;
+    float best_ms = 3.0e38f, best_all_ms = 3.0e38f, best_tb_ms = 3.0e38f;  // per sweep
     hipError_t err = hipSuccess;
     vec2_t<T> *pa = nullptr, *pb = nullptr;
-    for (int c = 0; c < kNumSweepConfigs && err == hipSuccess; ++c) {
+    for (int c = 0; c < kNumAllConfigs && err == hipSuccess; ++c) {
         if (!sweep_config_usable<T>(c, d, M)) {
             d.tune_us[pi][c] = -1.f;
             continue;
@@ -1439,8 +1703,12 @@ void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
             pb = ensure_packed<T>(d, 1, M.n);
             k_pack<T><<<(M.n + 255) / 256, 256, 0, s>>>(sx, sy, pa, pb, M.n);
         }
+        const bool tb = is_tb_config(c);
+        const int depth = sweep_config_depth(c);
         auto one = [&]() {
-            if (packed)
+            if (tb)
+                launch_tb_cfg<T>(c, d, M, pa, pb, depth, s);
+            else if (packed)
                 launch_sweep2_cfg<T>(c, d, M, pa, pb, nullptr, s);
             else
                 launch_sweep_cfg<T>(c, d, M, sx, sy, dx, dy, nullptr, s);
@@ -1453,15 +1721,20 @@ void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        ms /= float(reps * depth);
+        if (err == hipSuccess && tb && ms < best_tb_ms) {
+            best_tb_ms = ms;
+            best_tb = c;
+        }
         if (err == hipSuccess && !packed && ms < best_ms) {
             best_ms = ms;
             best = c;
         }
-        if (err == hipSuccess && ms < best_all_ms) {
+        if (err == hipSuccess && !tb && ms < best_all_ms) {
             best_all_ms = ms;
             best_all = c;
         }
-        d.tune_us[pi][c] = ms * 1000.f / float(reps);
+        d.tune_us[pi][c] = ms * 1000.f;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1469,12 +1742,16 @@ void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
     launch_check();
     d.sweep_cfg[pi] = best;
     d.smooth_cfg[pi] = best_all;
+    d.tb_cfg[pi] = best_tb >= 0 && best_tb_ms < best_all_ms ? best_tb : -1;
     if (env_flag("LMS_VERBOSE", false)) {
-        std::fprintf(stderr, "[lms] sweep autotune (%s, n=%d): %s, %.2f us (separate arrays: %s, %.2f us)\n",
-                     pi == 0 ? "f64" : "f32", M.n, sweep_config_name(best_all).c_str(),
-                     double(best_all_ms) * 1000.0 / reps, sweep_config_name(best).c_str(),
-                     double(best_ms) * 1000.0 / reps);
-        for (int c = 0; c < kNumSweepConfigs; ++c)
+        std::fprintf(stderr,
+                     "[lms] sweep autotune (%s, n=%d): %s, %.2f us (separate arrays: %s, %.2f us; "
+                     "temporally blocked: %s, %.2f us per sweep)\n",
+                     pi == 0 ? "f64" : "f32", M.n, sweep_config_name(best_all).c_str(), double(best_all_ms) * 1000.0,
+                     sweep_config_name(best).c_str(), double(best_ms) * 1000.0,
+                     best_tb >= 0 ? sweep_config_name(best_tb).c_str() : "none",
+                     best_tb >= 0 ? double(best_tb_ms) * 1000.0 : 0.0);
+        for (int c = 0; c < kNumAllConfigs; ++c)
             if (d.tune_us[pi][c] >= 0.f)
                 std::fprintf(stderr, "[lms]   %2d %-28s %9.2f us\n", c, sweep_config_name(c).c_str(),
                              double(d.tune_us[pi][c]));
@@ -1657,6 +1934,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     const int pi = sizeof(T) == 8 ? 0 : 1;
     const bool colour = sch == LMS_MULTICOLOR;
     const int cfg = colour ? -1 : d.smooth_cfg[pi];
+    const int tb = colour || o.check_quality ? -1 : d.tb_cfg[pi];
     vec2_t<T> *A = ensure_packed<T>(d, 0, M.n);
     vec2_t<T> *B = ensure_packed<T>(d, 1, M.n);
     const int nb = (M.n + 255) / 256;
@@ -1665,12 +1943,31 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     const std::string base = std::string("packed|") + (p == LMS_FP64 ? "f64" : "f32") + "|" + ptr_key(A) + "|" +
                              ptr_key(B) + "|cfg" + std::to_string(cfg) + "|" + std::to_string(int(sch));
     int32_t iters = 0;
+    bool in_b = false;  // the result sits in B
     const int small_rows = colour || o.check_quality ? 0 : small_batch_rows(M);
     if (small_rows > 0) {
         // every mesh of the batch fits in LDS: all K sweeps in one launch
         const int32_t K = o.max_iters;
         if (K > 0) launch_small_meshes<T>(d, M, A, B, K, small_rows, s);
         iters = K;
+        r.stopped_by = LMS_STOP_MAX_ITERS;
+        r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
+    } else if (tb >= 0) {
+        // temporally blocked: passes of up to `depth` sweeps, ping-pong A/B
+        const int32_t K = o.max_iters, depth = sweep_config_depth(tb);
+        const int32_t passes = (K + depth - 1) / depth;
+        if (K > 0)
+            run_maybe_graph(d, "tb|" + base + "|tb" + std::to_string(tb) + "|" + std::to_string(K), s,
+                            [&](hipStream_t cs) {
+                                int32_t left = K;
+                                for (int32_t q = 0; q < passes; ++q) {
+                                    const int32_t kk = std::min(left, depth);
+                                    launch_tb_cfg<T>(tb, d, M, q % 2 == 0 ? A : B, q % 2 == 0 ? B : A, kk, cs);
+                                    left -= kk;
+                                }
+                            });
+        iters = K;
+        in_b = passes % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
     } else if (!o.check_quality) {
@@ -1687,6 +1984,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                 }
             });
         iters = K;
+        in_b = !colour && K % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
     } else {
@@ -1720,8 +2018,9 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         r.q0 = h.q0;
         r.q_final = h.q_last;
         r.last_dq = h.last_dq;
+        in_b = !colour && iters % 2 == 1;
     }
-    k_unpack<T><<<nb, 256, 0, s>>>(!colour && iters % 2 == 1 ? B : A, x, y, M.n);
+    k_unpack<T><<<nb, 256, 0, s>>>(in_b ? B : A, x, y, M.n);
     launch_check();
     HIP_CHECK(hipStreamSynchronize(s));
     r.iters = iters;
@@ -1736,7 +2035,8 @@ void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precisi
             return;
         }
         tune_sweep<T>(d, M, x, y, tx, ty, s);
-        if (sweep_config_packed(d.smooth_cfg[sizeof(T) == 8 ? 0 : 1])) {
+        const int pi = sizeof(T) == 8 ? 0 : 1;
+        if (sweep_config_packed(d.smooth_cfg[pi]) || (!o.check_quality && d.tb_cfg[pi] >= 0)) {
             smooth_packed<T>(M, d, x, y, p, sch, o, s, r);
             return;
         }
@@ -1920,11 +2220,15 @@ void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p, 
 std::string dev_sweep_config(Mesh &M, lms_precision p) {
     check_precision(p);
     if (!M.dev || M.dev->version != M.version) return "";
-    const int c = M.dev->smooth_cfg[p == LMS_FP64 ? 0 : 1];
+    const int pi = p == LMS_FP64 ? 0 : 1;
+    const int c = M.dev->smooth_cfg[pi];
     if (c < 0) return "";
-    std::string out = sweep_config_name(c);
+    // first the variant a fixed-K Jacobi lms_smooth runs, then the one it
+    // runs under the stopping rule
+    std::string out = M.dev->tb_cfg[pi] >= 0 ? sweep_config_name(M.dev->tb_cfg[pi]) + " " + sweep_config_name(c)
+                                             : sweep_config_name(c);
     char buf[64];
-    for (int i = 0; i < kNumSweepConfigs; ++i) {
+    for (int i = 0; i < kNumAllConfigs; ++i) {
         std::snprintf(buf, sizeof(buf), "%s%d:%.2fus", i == 0 ? " tuned[" : " ", i,
                       double(M.dev->tune_us[p == LMS_FP64 ? 0 : 1][i]));
         out += buf;

@@ -427,6 +427,7 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
     }
 
     M.halo_plans.clear();
+    M.tb_plans.clear();
     M.ordering = kind;
     M.new2old = std::move(new2old);
     M.old2new = std::move(old2new);
@@ -514,6 +515,142 @@ const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts) {
     H.version = M.version;
     M.halo_plans.push_back(std::move(H));
     return M.halo_plans.back();
+}
+
+const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap) {
+    for (const auto &h : M.tb_plans)
+        if (h.ts == ts && h.k == k && h.u_cap == u_cap && h.l_cap == l_cap && h.version == M.version) return h;
+    if (M.ell_w <= 0) fail(LMS_ERR_STATE, "no padded adjacency for a temporal-blocking plan");
+    if (ts <= 0 || k < 1 || k > 8 || u_cap < 1 || l_cap < u_cap || l_cap >= 0xFFFF)
+        fail(LMS_ERR_ARG, "temporal-blocking plan: bad tile size, depth or caps");
+    Mesh::TBPlan P;
+    P.ts = ts;
+    P.k = k;
+    P.u_cap = u_cap;
+    P.l_cap = l_cap;
+    const int32_t n = M.n, W = M.ell_w;
+    P.tile_ptr.push_back(0);
+    P.halo_ptr.push_back(0);
+    P.lidx_ptr.push_back(0);
+    // stamp[v] == mark while a tile is tried; slot[v] is v's local slot then
+    std::vector<int32_t> stamp(size_t(n), 0), slot(size_t(n), 0), local;
+    int32_t mark = 0;
+    int32_t rc[9];
+    // Stage rows [b, e) and k rings; false as soon as a cap is exceeded.
+    auto try_tile = [&](int32_t b, int32_t e) {
+        if (++mark == std::numeric_limits<int32_t>::max()) {
+            std::fill(stamp.begin(), stamp.end(), 0);
+            mark = 1;
+        }
+        local.clear();
+        for (int32_t v = b; v < e; ++v) {
+            stamp[size_t(v)] = mark;
+            slot[size_t(v)] = v - b;
+            local.push_back(v);
+        }
+        rc[0] = e - b;
+        size_t from = 0;  // first local row of the ring being expanded
+        for (int32_t m = 1; m <= k; ++m) {
+            const size_t to = local.size();
+            for (size_t i = from; i < to; ++i) {
+                const int32_t v = local[i];
+                for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                    const int32_t u = M.col[size_t(j)];
+                    if (stamp[size_t(u)] == mark) continue;
+                    stamp[size_t(u)] = mark;
+                    local.push_back(u);
+                }
+                if (local.size() > size_t(l_cap)) return false;
+            }
+            std::sort(local.begin() + std::ptrdiff_t(to), local.end());
+            for (size_t i = to; i < local.size(); ++i) slot[size_t(local[i])] = int32_t(i);
+            rc[m] = int32_t(local.size());
+            from = to;
+        }
+        return rc[k - 1] <= u_cap;
+    };
+    auto emit_tile = [&](int32_t b, int32_t e) {
+        P.tile_ptr.push_back(e);
+        P.ring.insert(P.ring.end(), rc, rc + k + 1);
+        P.l_max = std::max(P.l_max, rc[k]);
+        P.u_max = std::max(P.u_max, rc[k - 1]);
+        P.halo.insert(P.halo.end(), local.begin() + (e - b), local.end());
+        P.halo_ptr.push_back(int64_t(P.halo.size()));
+        const size_t rows = size_t(rc[k - 1]);
+        const size_t base = P.lidx.size();
+        P.lidx.resize(base + rows * size_t(W), uint16_t(0xFFFF));
+        for (size_t i = 0; i < rows; ++i) {
+            const int32_t v = local[i];
+            uint16_t *row = P.lidx.data() + base + i * size_t(W);
+            for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                const int32_t u = M.col[size_t(j)];
+                if (stamp[size_t(u)] != mark) fail(LMS_ERR_STATE, "temporal-blocking plan: neighbour not staged");
+                row[j - M.row_ptr[v]] = uint16_t(slot[size_t(u)]);
+            }
+        }
+        P.lidx_ptr.push_back(P.lidx_ptr.back() + int64_t(rows));
+    };
+    std::vector<std::pair<int32_t, int32_t>> todo;
+    for (int64_t b0 = 0; b0 < n && P.fits; b0 += ts) {
+        todo.emplace_back(int32_t(b0), int32_t(std::min<int64_t>(n, b0 + ts)));
+        while (!todo.empty()) {
+            const auto [b, e] = todo.back();
+            todo.pop_back();
+            if (try_tile(b, e)) {
+                emit_tile(b, e);
+            } else if (e - b > 1) {  // halve; the left half goes first
+                const int32_t mid = b + (e - b) / 2;
+                todo.emplace_back(mid, e);
+                todo.emplace_back(b, mid);
+            } else {
+                P.fits = false;
+                break;
+            }
+        }
+    }
+    if (!P.fits) {
+        Mesh::TBPlan empty;
+        empty.ts = ts;
+        empty.k = k;
+        empty.u_cap = u_cap;
+        empty.l_cap = l_cap;
+        empty.fits = false;
+        P = std::move(empty);
+    } else {
+        P.tiles = int32_t(P.tile_ptr.size() - 1);
+        // self-check: tiles cover the rows in order; each updated row's slots
+        // name its CSR neighbours in order, inside the rows valid one sweep
+        // earlier (own + one more ring)
+        if (P.tile_ptr.back() != n) fail(LMS_ERR_STATE, "temporal-blocking plan: tiles do not cover the rows");
+        for (int32_t t = 0; t < P.tiles; ++t) {
+            const int32_t b = P.tile_ptr[size_t(t)], e = P.tile_ptr[size_t(t) + 1];
+            const int32_t *r = P.ring.data() + size_t(t) * size_t(k + 1);
+            const int64_t hb = P.halo_ptr[size_t(t)];
+            if (e <= b || r[0] != e - b || r[k] > l_cap || r[k - 1] > u_cap ||
+                P.halo_ptr[size_t(t) + 1] - hb != int64_t(r[k] - r[0]) ||
+                P.lidx_ptr[size_t(t) + 1] - P.lidx_ptr[size_t(t)] != int64_t(r[k - 1]))
+                fail(LMS_ERR_STATE, "temporal-blocking plan: tile counts");
+            auto global_of = [&](int32_t li) { return li < e - b ? b + li : P.halo[size_t(hb + li - (e - b))]; };
+            for (int32_t m = 0; m < k; ++m)
+                for (int32_t li = m == 0 ? 0 : r[m - 1]; li < r[m]; ++li) {
+                    const int32_t v = global_of(li);
+                    const uint16_t *row = P.lidx.data() + size_t(P.lidx_ptr[size_t(t)] + li) * size_t(W);
+                    const int32_t deg = M.row_ptr[v + 1] - M.row_ptr[v];
+                    for (int32_t q = 0; q < W; ++q) {
+                        if (q >= deg) {
+                            if (row[q] != 0xFFFF) fail(LMS_ERR_STATE, "temporal-blocking plan: padding slot in use");
+                            continue;
+                        }
+                        if (row[q] >= r[m + 1]) fail(LMS_ERR_STATE, "temporal-blocking plan: slot outside its ring");
+                        if (global_of(row[q]) != M.col[size_t(M.row_ptr[v] + q)])
+                            fail(LMS_ERR_STATE, "temporal-blocking plan: slot names the wrong vertex");
+                    }
+                }
+        }
+    }
+    P.version = M.version;
+    M.tb_plans.push_back(std::move(P));
+    return M.tb_plans.back();
 }
 
 }  // namespace lms

@@ -86,6 +86,33 @@ struct Mesh {
     };
     std::vector<HaloPlan> halo_plans;
 
+    // Tile plan of the temporally blocked sweep (k Jacobi sweeps per pass).
+    // Tiles are ranges of consecutive rows: nominally ts rows, halved until
+    // the tile's first sweep updates at most u_cap rows and its staging area
+    // holds at most l_cap rows.  Tile t stages its own rows (local slots
+    // 0..own-1) and k halo rings: ring 1 holds the outside neighbours of its
+    // rows, ring m+1 the neighbours of ring m's free rows not staged yet, each
+    // ring in ascending id.  ring[t*(k+1)+m] counts the rows of own + rings
+    // 1..m.  Sweep j of a pass of k' <= k sweeps updates the rows below
+    // ring[t*(k+1)+k'-j]; their padded slots (0xFFFF past a row's end) come
+    // first in the tile's lidx block.  fits is false when even a one-row
+    // tile exceeds the caps (the plan is then empty).
+    struct TBPlan {
+        int32_t ts = 0, k = 0, u_cap = 0, l_cap = 0;
+        bool fits = true;
+        int32_t tiles = 0;
+        int32_t l_max = 0;  // largest staging area (rows), over tiles
+        int32_t u_max = 0;  // largest first-sweep update set (rows), over tiles
+        std::vector<int32_t> tile_ptr;  // tiles+1: first own row of each tile
+        std::vector<int32_t> ring;      // tiles * (k+1)
+        std::vector<int64_t> halo_ptr;  // tiles+1, into halo
+        std::vector<int32_t> halo;      // per tile: rings 1..k
+        std::vector<int64_t> lidx_ptr;  // tiles+1, in rows of ell_w slots
+        std::vector<uint16_t> lidx;
+        uint64_t version = ~uint64_t(0);
+    };
+    std::vector<TBPlan> tb_plans;
+
     // generation counter: bumped whenever the current labelling changes so
     // that device copies and captured graphs are refreshed
     uint64_t version = 0;
@@ -102,6 +129,7 @@ std::vector<int32_t> order_rdr(const Mesh &M, const double *q);
 std::vector<int32_t> order_random(const Mesh &M, uint64_t seed);
 void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old);
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
+const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap);
 
 // ---- device runtime (lms_device.hip) ----
 void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,

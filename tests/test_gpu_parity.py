@@ -352,7 +352,7 @@ def test_every_sweep_variant_gives_the_same_bits(width):
     ref = {}
     ran = 0
     try:
-        for cfg in range(44):
+        for cfg in range(56):
             os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
             for dt in (torch.float64, torch.float32):
                 try:
@@ -362,8 +362,8 @@ def test_every_sweep_variant_gives_the_same_bits(width):
                     continue
                 ran += 1
                 name = M.sweep_config("f64" if dt == torch.float64 else "f32")
-                assert name.startswith(("row/", "lds/", "ell/", "ell2/", "row2/", "halo/"))
-                if name.startswith(("ell/", "ell2/", "halo/")):
+                assert name.startswith(("row/", "lds/", "ell/", "ell2/", "row2/", "halo/", "tb/"))
+                if name.startswith(("ell/", "ell2/", "halo/", "tb/")):
                     assert f"/w{width}/" in name
                 ref.setdefault(str(dt), (x, y))
                 assert np.array_equal(x, ref[str(dt)][0]) and np.array_equal(y, ref[str(dt)][1]), cfg
@@ -381,7 +381,7 @@ def test_autotuned_sweep_matches_oracle_and_reports_choice():
     ex, ey = osm.jacobi(top, m.x, m.y, 6)
     x, y, _, M = run_library(m, "bfs", 6)
     name = M.sweep_config("f64")
-    assert name.split("/")[0] in ("row", "lds", "ell", "ell2", "row2", "halo")
+    assert name.split("/")[0] in ("row", "lds", "ell", "ell2", "row2", "halo", "tb")
     assert "tuned[" in name and M.sweep_config("f32") == ""
     M.reorder("random", seed=1)                  # a new ordering is tuned afresh
     assert M.sweep_config("f64") == "" and isinstance(lms.ORI, int)
@@ -479,3 +479,48 @@ def test_small_mesh_batch_in_one_launch(prec, K, sizes):
             seg = slice(v_off[i], v_off[i + 1])
             assert np.max(np.abs(outs[0][0][seg] - ex)) <= TOL64 * extent(m.xy)
             assert np.max(np.abs(outs[0][1][seg] - ey)) <= TOL64 * extent(m.xy)
+
+
+@pytest.mark.parametrize("kind", ["rdr", "bfs", "ori"])
+def test_temporal_blocking_same_bits_as_single_sweeps(kind):
+    # k sweeps per pass (a tile and k halo rings advanced in LDS) against one
+    # sweep per pass: the same bits, for K below, at and past the depth, with
+    # a ragged last pass, in both precisions; and the oracle in float64
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    m = meshgen.jittered_grid(301, 277, seed=31, land_fraction=0.3)
+    top = oracle_topology(m)
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    try:
+        for K in (1, 2, 5, 9):
+            ex, ey = osm.jacobi(top, m.x, m.y, K)
+            for dt in (torch.float64, torch.float32):
+                os.environ["LMS_SWEEP_CONFIG"] = "36"       # one sweep per pass (halo-staged)
+                rx, ry, _, _ = run_library(m, kind, K, dtype=dt, M=M)
+                for cfg in range(44, 52):                    # width 8: depths 2, 2, 2, 2, 3, 3, 2, 4
+                    os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
+                    x, y, r, _ = run_library(m, kind, K, dtype=dt, M=M)
+                    assert M.sweep_config("f64" if dt == torch.float64 else "f32").startswith("tb/")
+                    assert r["iters"] == K
+                    assert np.array_equal(x, rx) and np.array_equal(y, ry), (cfg, K, str(dt))
+                if dt == torch.float64:
+                    assert np.max(np.abs(rx - ex)) <= TOL64 * extent(m.xy)
+                    assert np.max(np.abs(ry - ey)) <= TOL64 * extent(m.xy)
+    finally:
+        os.environ.pop("LMS_SWEEP_CONFIG", None)
+
+
+def test_temporal_blocking_under_the_stopping_rule_uses_single_sweeps():
+    # the stopping rule needs Q after every sweep: a forced temporally blocked
+    # variant leaves it on one sweep per pass, with the oracle's stop sweep
+    from paper_1606_00803_amd import lms
+    m = meshgen.jittered_grid(120, 110, seed=32, land_fraction=0.3)
+    ref = osm.smooth(oracle_topology(m), m.x, m.y, max_iters=500)
+    assert ref.stopped_by == "tol"
+    os.environ["LMS_SWEEP_CONFIG"] = "46"
+    try:
+        x, y, r, M = run_library(m, "rdr", 500, check_quality=True)
+    finally:
+        os.environ.pop("LMS_SWEEP_CONFIG", None)
+    assert r["iters"] == ref.iters
+    assert np.max(np.abs(x - ref.x)) <= TOL64 * extent(m.xy)
