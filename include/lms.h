@@ -170,8 +170,13 @@ lms_status lms_permute(lms_mesh_t m, const void *sx, const void *sy, void *dx, v
  *   s       LMS_JACOBI (every free vertex reads the previous sweep's values)
  *           or LMS_MULTICOLOR
  *   o       options (NULL = lms_smooth_opts_default)
- *   r       host out, or NULL
- * The stream is synchronised before return. */
+ *   r       host out, or NULL (filled on return)
+ * Asynchronous on `stream`: x, y hold the result once the stream reaches the
+ * end of the call.  Under the stopping rule the host reads the stop state
+ * between chunks of sweeps, so that path waits for the stream as it runs.
+ * Calls on one handle from different streams are ordered by the handle (each
+ * waits for the previous call); the caller orders its own reads and writes of
+ * x, y (and tx, ty) with the stream. */
 lms_status lms_smooth(lms_mesh_t m, void *x, void *y, void *tx, void *ty,
                       lms_precision p, lms_scheme s, const lms_smooth_opts *o,
                       void *stream, lms_smooth_result *r);
@@ -195,12 +200,15 @@ lms_status lms_quality(lms_mesh_t m, const void *x, const void *y, lms_precision
 lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_precision p,
                                double *q_mesh, void *stream);
 
-/* Name of the sweep kernel variant chosen for precision p, followed by the
- * per-variant timings the autotuner measured ("" until the first lms_smooth
- * or lms_sweep of that precision since the last reorder).  The first sweep
- * call per precision and ordering times every variant on the caller's
- * stream (synchronously) and keeps the fastest; all variants give identical
- * results.  buf: host char[len] out, NUL-terminated. */
+/* Name of the sweep kernel variant a fixed-K Jacobi lms_smooth runs for
+ * precision p (when that is a temporally blocked variant, k sweeps per pass,
+ * the single-sweep variant used under the stopping rule follows it), then
+ * the per-variant timings the autotuner measured, in microseconds per sweep
+ * ("" until the first lms_smooth or lms_sweep of that precision since the
+ * last reorder).  The first sweep call per precision and ordering times every
+ * variant on the caller's stream (synchronously) and keeps the fastest; all
+ * variants give identical results.  buf: host char[len] out, NUL-terminated,
+ * truncated to len-1 characters. */
 lms_status lms_sweep_config(lms_mesh_t m, lms_precision p, char *buf, int32_t len);
 
 /* Free the handle and everything it owns.  NULL is accepted. */

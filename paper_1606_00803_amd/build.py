@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for s in HOST_SRC:
         o = os.path.join(BUILD, s + ".o")
-        _run(["g++", *COMMON, "-c", os.path.join(CSRC, s), "-o", o])
+        _run(["g++", *COMMON, "-pthread", "-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     hipcc = _hipcc()
     for s in HIP_SRC:
@@ -60,7 +60,7 @@ def build(verbose: bool = False) -> str:
               "-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-pthread", "-o", tmp])
     os.replace(tmp, LIB)
     if verbose:
         print(LIB)

@@ -594,10 +594,12 @@ __device__ __forceinline__ void load_slot_words(const uint16_t *__restrict__ row
 // stores, waits; the last one writes the own free rows to dst.  Thread t
 // owns local rows t, t+BS, ..., R of them; the plan guarantees that the
 // rows updated by the first sweep fit (ring[k-1] <= BS*R) and that the
-// staging area fits the dynamic LDS it is launched with.
-template <typename T, int BS, int W, int R, int MAP>
+// staging area fits the dynamic LDS it is launched with.  TS (nominal tile
+// size), KP (the plan's depth) and LCAP (its staging cap) name the variant
+// whose plan the kernel reads; the tiles themselves come from tile_ptr.
+template <typename T, int BS, int W, int R, int MAP, int TS, int KP, int LCAP>
 __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ tile_ptr,
-                                                  const int32_t *__restrict__ ring, int32_t kp, int32_t k,
+                                                  const int32_t *__restrict__ ring, int32_t k,
                                                   const int64_t *__restrict__ halo_ptr,
                                                   const int32_t *__restrict__ halo,
                                                   const int64_t *__restrict__ lidx_ptr,
@@ -609,7 +611,8 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
     const int tid = int(threadIdx.x);
     const int32_t b = tile_ptr[tile];
-    const int32_t *rc = ring + int64_t(tile) * (kp + 1);
+    static_assert(KP >= 1 && KP <= 8 && TS > 0 && LCAP > 0, "plan shape");
+    const int32_t *rc = ring + int64_t(tile) * (KP + 1);
     const int32_t nown = rc[0], nload = rc[k], nupd = rc[k - 1];
     const int64_t hb = halo_ptr[tile], lb = lidx_ptr[tile];
     uint32_t wd[R][W / 2];
@@ -1116,6 +1119,12 @@ struct DeviceState {
     int sweep_cfg[2] = {-1, -1};     // separate-array sweep variant per precision, -1 = not tuned
     int smooth_cfg[2] = {-1, -1};    // variant lms_smooth uses (may sweep the interleaved copy)
     int tb_cfg[2] = {-1, -1};        // temporally blocked variant for fixed-K Jacobi, -1 = none
+    // end of the handle's last device call: a call on another stream waits
+    // for it (the handle's buffers are shared between calls), and nothing the
+    // calls may use is freed before it
+    hipEvent_t last_done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool last_valid = false;
     void *pk[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [precision][ping|pong] interleaved copies
     size_t pk_n[2] = {0, 0};
     float tune_us[2][64] = {};       // measured time per variant (microseconds per sweep)
@@ -1129,6 +1138,22 @@ void free_graphs(DeviceState *d) {
         if (g.graph) (void)hipGraphDestroy(g.graph);
     }
     d->graphs.clear();
+}
+
+// Wait until the handle's last device call has finished on the device.
+void wait_idle(DeviceState &d) {
+    if (d.last_valid) HIP_CHECK(hipEventSynchronize(d.last_done));
+}
+
+// Order this call after the handle's last one when it ran on another stream.
+void begin_call(DeviceState &d, hipStream_t s) {
+    if (d.last_valid && d.last_stream != s) HIP_CHECK(hipStreamWaitEvent(s, d.last_done, 0));
+}
+
+void end_call(DeviceState &d, hipStream_t s) {
+    HIP_CHECK(hipEventRecord(d.last_done, s));
+    d.last_stream = s;
+    d.last_valid = true;
 }
 
 void free_arrays(DeviceState *d) {
@@ -1167,12 +1192,14 @@ DeviceState &ensure_device(Mesh &M) {
         HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d->qout), sizeof(double)));
         HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d->st), sizeof(StopState)));
         HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&d->h_st), sizeof(StopState), hipHostMallocDefault));
+        HIP_CHECK(hipEventCreateWithFlags(&d->last_done, hipEventDisableTiming));
     }
     DeviceState *d = M.dev.get();
     if (d->device != dev)
         fail(LMS_ERR_STATE, "handle lives on device " + std::to_string(d->device) + " but device " +
                                 std::to_string(dev) + " is current");
     if (d->version != M.version) {
+        wait_idle(*d);
         free_graphs(d);
         free_arrays(d);
         d->halos.clear();  // their arrays were in d->arrays
@@ -1285,20 +1312,29 @@ constexpr int kDefaultSweepConfig = 0;
 // than block size x rows per thread rows, or whose staging area would pass
 // the cap, is halved until it fits.
 #define LMS_TB_CONFIGS(TB)                 \
-    TB(44, 128, 8, 4, 0, 128, 2, 1024)     \
+    TB(44, 128, 8, 2, 0, 128, 2, 512)      \
     TB(45, 256, 8, 2, 0, 256, 2, 1024)     \
-    TB(46, 256, 8, 4, 0, 256, 2, 2048)     \
-    TB(47, 256, 8, 4, 0, 512, 2, 2048)     \
-    TB(48, 256, 8, 4, 0, 256, 3, 2048)     \
-    TB(49, 256, 8, 8, 0, 512, 3, 4096)     \
-    TB(50, 256, 8, 8, 0, 1024, 2, 4096)    \
-    TB(51, 512, 8, 8, 0, 512, 4, 4096)     \
-    TB(52, 256, 12, 4, 0, 512, 2, 2048)    \
-    TB(53, 256, 12, 8, 0, 1024, 2, 4096)   \
-    TB(54, 256, 12, 4, 0, 256, 3, 2048)    \
-    TB(55, 256, 16, 4, 0, 512, 2, 2048)
+    TB(46, 256, 8, 2, -1, 256, 2, 1024)    \
+    TB(47, 256, 8, 2, 16, 256, 2, 1024)    \
+    TB(48, 256, 8, 4, 0, 256, 2, 2048)     \
+    TB(49, 256, 8, 4, 0, 512, 2, 2048)     \
+    TB(50, 256, 8, 4, -1, 512, 2, 2048)    \
+    TB(51, 256, 8, 4, 0, 256, 3, 2048)     \
+    TB(52, 256, 8, 8, 0, 512, 3, 4096)     \
+    TB(53, 256, 8, 8, 0, 1024, 2, 4096)    \
+    TB(54, 512, 8, 8, 0, 512, 4, 4096)     \
+    TB(55, 128, 8, 2, 16, 128, 2, 512)     \
+    TB(56, 256, 12, 4, 0, 512, 2, 2048)    \
+    TB(57, 256, 12, 4, -1, 512, 2, 2048)   \
+    TB(58, 256, 12, 8, 0, 1024, 2, 4096)   \
+    TB(59, 256, 12, 4, 0, 256, 3, 2048)    \
+    TB(60, 256, 12, 2, 0, 256, 2, 1024)    \
+    TB(61, 256, 16, 4, 0, 512, 2, 2048)    \
+    TB(62, 256, 16, 2, 0, 256, 2, 1024)    \
+    TB(63, 256, 16, 4, -1, 512, 2, 2048)
 constexpr int kFirstTBConfig = kNumSweepConfigs;
-constexpr int kNumAllConfigs = 56;
+constexpr int kNumAllConfigs = 64;
+static_assert(kNumAllConfigs <= 64, "tune_us holds 64 variants");
 
 struct TBShape {
     int bs = 0, w = 0, r = 0, map = 0, ts = 0, k = 0, lcap = 0;
@@ -1581,8 +1617,8 @@ void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T>
     switch (cfg) {
 #define TB(id, bs, w, r, map, ts, kk, lcap)                                                                    \
     case id:                                                                                                   \
-        k_jacobi_tb<T, bs, w, r, map><<<h->tiles, bs, lds, s>>>(h->tile_ptr, h->ring, t.k, k, h->halo_ptr,     \
-                                                                 h->halo, h->lidx_ptr, h->lidx, src, dst);      \
+        k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap><<<h->tiles, bs, lds, s>>>(                               \
+            h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst);                     \
         break;
         LMS_TB_CONFIGS(TB)
 #undef TB
@@ -1645,6 +1681,7 @@ template <typename T>
 vec2_t<T> *ensure_packed(DeviceState &d, int which, int32_t n) {
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (d.pk_n[pi] < size_t(n)) {
+        wait_idle(d);
         for (int w = 0; w < 2; ++w) {
             if (d.pk[pi][w]) (void)hipFree(d.pk[pi][w]);
             d.pk[pi][w] = nullptr;
@@ -1860,6 +1897,7 @@ std::string dbl_key(double v) {
 void *ensure_tmp(DeviceState &d, lms_precision p, int which, int32_t n) {
     const int pi = p == LMS_FP64 ? 0 : 1;
     if (d.tmp_n[pi] < size_t(n)) {
+        wait_idle(d);
         for (int w = 0; w < 2; ++w) {
             if (d.tmp[pi][w]) (void)hipFree(d.tmp[pi][w]);
             d.tmp[pi][w] = nullptr;
@@ -2022,7 +2060,6 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     }
     k_unpack<T><<<nb, 256, 0, s>>>(in_b ? B : A, x, y, M.n);
     launch_check();
-    HIP_CHECK(hipStreamSynchronize(s));
     r.iters = iters;
 }
 
@@ -2074,7 +2111,6 @@ void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precisi
             HIP_CHECK(hipMemcpyAsync(x, tx, bytes, hipMemcpyDeviceToDevice, s));
             HIP_CHECK(hipMemcpyAsync(y, ty, bytes, hipMemcpyDeviceToDevice, s));
         }
-        HIP_CHECK(hipStreamSynchronize(s));
         r.iters = K;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
@@ -2113,7 +2149,6 @@ void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precisi
     if (jacobi && (h.iters % 2 == 1)) {
         HIP_CHECK(hipMemcpyAsync(x, tx, bytes, hipMemcpyDeviceToDevice, s));
         HIP_CHECK(hipMemcpyAsync(y, ty, bytes, hipMemcpyDeviceToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));
     }
     r.iters = h.iters;
     r.stopped_by = h.stopped_by;
@@ -2129,6 +2164,7 @@ void destroy_device_state(DeviceState *d) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     if (d->device >= 0) (void)hipSetDevice(d->device);
+    if (d->last_valid) (void)hipEventSynchronize(d->last_done);
     free_graphs(d);
     free_arrays(d);
     for (auto &pt : d->tmp)
@@ -2143,6 +2179,7 @@ void destroy_device_state(DeviceState *d) {
     if (d->st) (void)hipFree(d->st);
     if (d->h_st) (void)hipHostFree(d->h_st);
     if (d->cap) (void)hipStreamDestroy(d->cap);
+    if (d->last_done) (void)hipEventDestroy(d->last_done);
     if (cur >= 0) (void)hipSetDevice(cur);
     delete d;
 }
@@ -2156,6 +2193,7 @@ void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lm
         fail(LMS_ERR_ARG, "lms_permute source and destination overlap");
     DeviceState &d = ensure_device(M);
     hipStream_t s = as_stream(stream);
+    begin_call(d, s);
     const int nb = (M.n + 255) / 256;
     if (p == LMS_FP64)
         k_permute<double><<<nb, 256, 0, s>>>(d.new2old, static_cast<const double *>(sx), static_cast<const double *>(sy),
@@ -2164,6 +2202,7 @@ void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lm
         k_permute<float><<<nb, 256, 0, s>>>(d.new2old, static_cast<const float *>(sx), static_cast<const float *>(sy),
                                             static_cast<float *>(dx), static_cast<float *>(dy), M.n, inverse);
     launch_check();
+    end_call(d, s);
 }
 
 void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lms_precision p, void *stream) {
@@ -2174,6 +2213,7 @@ void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lms_
         fail(LMS_ERR_ARG, "a Jacobi sweep cannot run in place");
     DeviceState &d = ensure_device(M);
     hipStream_t s = as_stream(stream);
+    begin_call(d, s);
     if (p == LMS_FP64) {
         tune_sweep<double>(d, M, static_cast<const double *>(sx), static_cast<const double *>(sy),
                            static_cast<double *>(dx), static_cast<double *>(dy), s);
@@ -2186,6 +2226,7 @@ void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy, lms_
                             static_cast<float *>(dx), static_cast<float *>(dy), nullptr, s);
     }
     launch_check();
+    end_call(d, s);
 }
 
 void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p, lms_scheme sch,
@@ -2198,6 +2239,8 @@ void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p, 
     const size_t bytes = elem_size(p) * size_t(M.n);
     if (overlaps(x, y, bytes)) fail(LMS_ERR_ARG, "x and y overlap");
     DeviceState &d = ensure_device(M);
+    hipStream_t s = as_stream(stream);
+    begin_call(d, s);
     if (sch == LMS_JACOBI) {
         if ((tx == nullptr) != (ty == nullptr)) fail(LMS_ERR_ARG, "give both tx and ty, or neither");
         if (!tx) {
@@ -2208,13 +2251,13 @@ void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p, 
             overlaps(ty, y, bytes))
             fail(LMS_ERR_ARG, "Jacobi scratch buffers must not overlap the coordinates");
     }
-    hipStream_t s = as_stream(stream);
     if (p == LMS_FP64)
         smooth_typed<double>(M, d, static_cast<double *>(x), static_cast<double *>(y), static_cast<double *>(tx),
                              static_cast<double *>(ty), p, sch, o, s, r);
     else
         smooth_typed<float>(M, d, static_cast<float *>(x), static_cast<float *>(y), static_cast<float *>(tx),
                             static_cast<float *>(ty), p, sch, o, s, r);
+    end_call(d, s);
 }
 
 std::string dev_sweep_config(Mesh &M, lms_precision p) {
@@ -2242,6 +2285,7 @@ void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double 
     if (!x || !y) fail(LMS_ERR_ARG, "null coordinate pointer");
     DeviceState &d = ensure_device(M);
     hipStream_t s = as_stream(stream);
+    begin_call(d, s);
     if (q_mesh) {
         if (p == LMS_FP64)
             k_quality_mesh<double><<<M.n_mesh, 256, 0, s>>>(d.ta, d.tb, d.tc, d.tw, static_cast<const double *>(x),
@@ -2252,11 +2296,13 @@ void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double 
         launch_check();
         HIP_CHECK(hipMemcpyAsync(q_mesh, d.qmesh, sizeof(double) * size_t(M.n_mesh), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
+        end_call(d, s);
         return;
     }
     double *qt_out = nullptr;
     if (q_vertex) {
         if (d.qt_cap < size_t(M.T)) {
+            wait_idle(d);
             if (d.qt) (void)hipFree(d.qt);
             d.qt = nullptr;
             d.qt_cap = 0;
@@ -2280,6 +2326,7 @@ void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double 
         HIP_CHECK(hipMemcpyAsync(q_global, d.qout, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
     }
+    end_call(d, s);
 }
 
 }  // namespace lms

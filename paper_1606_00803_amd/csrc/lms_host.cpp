@@ -8,8 +8,10 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <limits>
 #include <numeric>
+#include <thread>
 
 #include "lms_internal.hpp"
 
@@ -517,136 +519,249 @@ const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts) {
     return M.halo_plans.back();
 }
 
+namespace {
+
+// Open-addressing map vertex id -> local slot for one tile at a time; clear()
+// empties only the entries the last tile used.
+class SlotMap {
+   public:
+    explicit SlotMap(size_t want) {
+        size_t cap = 16;
+        while (cap < 2 * want) cap *= 2;
+        keys_.assign(cap, -1);
+        vals_.assign(cap, 0);
+        mask_ = cap - 1;
+    }
+    // inserts (v, slot) unless v is present; true when inserted
+    bool insert(int32_t v, int32_t slot) {
+        size_t h = hash(v);
+        while (keys_[h] != -1) {
+            if (keys_[h] == v) return false;
+            h = (h + 1) & mask_;
+        }
+        keys_[h] = v;
+        vals_[h] = slot;
+        used_.push_back(h);
+        return true;
+    }
+    bool contains(int32_t v) const { return find(v) != npos; }
+    void set(int32_t v, int32_t slot) { vals_[find(v)] = slot; }
+    int32_t get(int32_t v) const {
+        const size_t h = find(v);
+        return h == npos ? -1 : vals_[h];
+    }
+    void clear() {
+        for (size_t h : used_) keys_[h] = -1;
+        used_.clear();
+    }
+
+   private:
+    static constexpr size_t npos = ~size_t(0);
+    size_t hash(int32_t v) const { return size_t((uint32_t(v) * 2654435761u) >> 7) & mask_; }
+    size_t find(int32_t v) const {
+        size_t h = hash(v);
+        while (keys_[h] != -1) {
+            if (keys_[h] == v) return h;
+            h = (h + 1) & mask_;
+        }
+        return npos;
+    }
+    std::vector<int32_t> keys_, vals_;
+    std::vector<size_t> used_;
+    size_t mask_ = 0;
+};
+
+// The tiles one worker builds for a run of nominal tiles.
+struct TBPart {
+    bool fits = true;
+    std::vector<int32_t> tile_end, ring, halo, halo_n, lidx_rows;
+    std::vector<uint16_t> lidx;
+    int32_t l_max = 0, u_max = 0;
+};
+
+int host_threads(int64_t work_items) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t t = std::min<int64_t>(std::min<int64_t>(hw == 0 ? 1 : hw, 16), std::max<int64_t>(1, work_items / 64));
+    return int(std::max<int64_t>(1, t));
+}
+
+// Runs f(worker, first, last) over [0, items) split into contiguous runs,
+// one thread each; rethrows the first exception.
+template <class F>
+void parallel_runs(int64_t items, int workers, F f) {
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(static_cast<size_t>(workers));
+    for (int w = 0; w < workers; ++w) {
+        const int64_t first = items * w / workers, last = items * (w + 1) / workers;
+        th.emplace_back([&, w, first, last]() {
+            try {
+                f(w, first, last);
+            } catch (...) {
+                err[size_t(w)] = std::current_exception();
+            }
+        });
+    }
+    for (auto &t : th) t.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
+}  // namespace
+
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap) {
     for (const auto &h : M.tb_plans)
         if (h.ts == ts && h.k == k && h.u_cap == u_cap && h.l_cap == l_cap && h.version == M.version) return h;
     if (M.ell_w <= 0) fail(LMS_ERR_STATE, "no padded adjacency for a temporal-blocking plan");
     if (ts <= 0 || k < 1 || k > 8 || u_cap < 1 || l_cap < u_cap || l_cap >= 0xFFFF)
         fail(LMS_ERR_ARG, "temporal-blocking plan: bad tile size, depth or caps");
+    const int32_t n = M.n, W = M.ell_w;
+    const int64_t nominal = (int64_t(n) + ts - 1) / ts;
+    const int workers = host_threads(nominal);
+    std::vector<TBPart> parts(static_cast<size_t>(workers));
+    parallel_runs(nominal, workers, [&](int w, int64_t first, int64_t last) {
+        TBPart &out = parts[size_t(w)];
+        SlotMap slots(size_t(l_cap) + size_t(W) + 1);
+        std::vector<int32_t> local;
+        int32_t rc[9];
+        // Stage rows [b, e) and k rings; false as soon as a cap is exceeded.
+        auto try_tile = [&](int32_t b, int32_t e) {
+            slots.clear();
+            local.clear();
+            for (int32_t v = b; v < e; ++v) {
+                slots.insert(v, v - b);
+                local.push_back(v);
+            }
+            rc[0] = e - b;
+            if (rc[0] > l_cap) return false;
+            size_t from = 0;  // first local row of the ring being expanded
+            for (int32_t m = 1; m <= k; ++m) {
+                const size_t to = local.size();
+                for (size_t i = from; i < to; ++i) {
+                    const int32_t v = local[i];
+                    for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                        const int32_t u = M.col[size_t(j)];
+                        if (slots.insert(u, -1)) local.push_back(u);
+                    }
+                    if (local.size() > size_t(l_cap)) return false;
+                }
+                std::sort(local.begin() + std::ptrdiff_t(to), local.end());
+                for (size_t i = to; i < local.size(); ++i) slots.set(local[i], int32_t(i));
+                rc[m] = int32_t(local.size());
+                from = to;
+            }
+            return rc[k - 1] <= u_cap;
+        };
+        auto emit_tile = [&](int32_t b, int32_t e) {
+            out.tile_end.push_back(e);
+            out.ring.insert(out.ring.end(), rc, rc + k + 1);
+            out.l_max = std::max(out.l_max, rc[k]);
+            out.u_max = std::max(out.u_max, rc[k - 1]);
+            out.halo.insert(out.halo.end(), local.begin() + (e - b), local.end());
+            out.halo_n.push_back(rc[k] - rc[0]);
+            const size_t rows = size_t(rc[k - 1]);
+            const size_t base = out.lidx.size();
+            out.lidx.resize(base + rows * size_t(W), uint16_t(0xFFFF));
+            for (size_t i = 0; i < rows; ++i) {
+                const int32_t v = local[i];
+                uint16_t *row = out.lidx.data() + base + i * size_t(W);
+                for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                    const int32_t s = slots.get(M.col[size_t(j)]);
+                    if (s < 0) fail(LMS_ERR_STATE, "temporal-blocking plan: neighbour not staged");
+                    row[j - M.row_ptr[v]] = uint16_t(s);
+                }
+            }
+            out.lidx_rows.push_back(int32_t(rows));
+        };
+        std::vector<std::pair<int32_t, int32_t>> todo;
+        for (int64_t t = first; t < last && out.fits; ++t) {
+            todo.emplace_back(int32_t(t * ts), int32_t(std::min<int64_t>(n, (t + 1) * ts)));
+            while (!todo.empty()) {
+                const auto [b, e] = todo.back();
+                todo.pop_back();
+                if (try_tile(b, e)) {
+                    emit_tile(b, e);
+                } else if (e - b > 1) {  // halve; the left half goes first
+                    const int32_t mid = b + (e - b) / 2;
+                    todo.emplace_back(mid, e);
+                    todo.emplace_back(b, mid);
+                } else {
+                    out.fits = false;
+                    break;
+                }
+            }
+        }
+    });
     Mesh::TBPlan P;
     P.ts = ts;
     P.k = k;
     P.u_cap = u_cap;
     P.l_cap = l_cap;
-    const int32_t n = M.n, W = M.ell_w;
-    P.tile_ptr.push_back(0);
-    P.halo_ptr.push_back(0);
-    P.lidx_ptr.push_back(0);
-    // stamp[v] == mark while a tile is tried; slot[v] is v's local slot then
-    std::vector<int32_t> stamp(size_t(n), 0), slot(size_t(n), 0), local;
-    int32_t mark = 0;
-    int32_t rc[9];
-    // Stage rows [b, e) and k rings; false as soon as a cap is exceeded.
-    auto try_tile = [&](int32_t b, int32_t e) {
-        if (++mark == std::numeric_limits<int32_t>::max()) {
-            std::fill(stamp.begin(), stamp.end(), 0);
-            mark = 1;
+    for (const auto &q : parts) P.fits = P.fits && q.fits;
+    if (P.fits) {
+        size_t tiles = 0, halo = 0, lidx = 0;
+        for (const auto &q : parts) {
+            tiles += q.tile_end.size();
+            halo += q.halo.size();
+            lidx += q.lidx.size();
         }
-        local.clear();
-        for (int32_t v = b; v < e; ++v) {
-            stamp[size_t(v)] = mark;
-            slot[size_t(v)] = v - b;
-            local.push_back(v);
-        }
-        rc[0] = e - b;
-        size_t from = 0;  // first local row of the ring being expanded
-        for (int32_t m = 1; m <= k; ++m) {
-            const size_t to = local.size();
-            for (size_t i = from; i < to; ++i) {
-                const int32_t v = local[i];
-                for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
-                    const int32_t u = M.col[size_t(j)];
-                    if (stamp[size_t(u)] == mark) continue;
-                    stamp[size_t(u)] = mark;
-                    local.push_back(u);
-                }
-                if (local.size() > size_t(l_cap)) return false;
+        if (tiles >= size_t(std::numeric_limits<int32_t>::max())) fail(LMS_ERR_STATE, "too many tiles");
+        P.tiles = int32_t(tiles);
+        P.tile_ptr.reserve(tiles + 1);
+        P.halo_ptr.reserve(tiles + 1);
+        P.lidx_ptr.reserve(tiles + 1);
+        resize_or_fail(P.halo, halo);
+        resize_or_fail(P.lidx, lidx);
+        P.ring.reserve(tiles * size_t(k + 1));
+        P.tile_ptr.push_back(0);
+        P.halo_ptr.push_back(0);
+        P.lidx_ptr.push_back(0);
+        size_t ho = 0, lo = 0;
+        for (auto &q : parts) {
+            P.l_max = std::max(P.l_max, q.l_max);
+            P.u_max = std::max(P.u_max, q.u_max);
+            P.ring.insert(P.ring.end(), q.ring.begin(), q.ring.end());
+            for (size_t t = 0; t < q.tile_end.size(); ++t) {
+                P.tile_ptr.push_back(q.tile_end[t]);
+                P.halo_ptr.push_back(P.halo_ptr.back() + q.halo_n[t]);
+                P.lidx_ptr.push_back(P.lidx_ptr.back() + q.lidx_rows[t]);
             }
-            std::sort(local.begin() + std::ptrdiff_t(to), local.end());
-            for (size_t i = to; i < local.size(); ++i) slot[size_t(local[i])] = int32_t(i);
-            rc[m] = int32_t(local.size());
-            from = to;
+            std::copy(q.halo.begin(), q.halo.end(), P.halo.begin() + std::ptrdiff_t(ho));
+            std::copy(q.lidx.begin(), q.lidx.end(), P.lidx.begin() + std::ptrdiff_t(lo));
+            ho += q.halo.size();
+            lo += q.lidx.size();
+            q = TBPart{};
         }
-        return rc[k - 1] <= u_cap;
-    };
-    auto emit_tile = [&](int32_t b, int32_t e) {
-        P.tile_ptr.push_back(e);
-        P.ring.insert(P.ring.end(), rc, rc + k + 1);
-        P.l_max = std::max(P.l_max, rc[k]);
-        P.u_max = std::max(P.u_max, rc[k - 1]);
-        P.halo.insert(P.halo.end(), local.begin() + (e - b), local.end());
-        P.halo_ptr.push_back(int64_t(P.halo.size()));
-        const size_t rows = size_t(rc[k - 1]);
-        const size_t base = P.lidx.size();
-        P.lidx.resize(base + rows * size_t(W), uint16_t(0xFFFF));
-        for (size_t i = 0; i < rows; ++i) {
-            const int32_t v = local[i];
-            uint16_t *row = P.lidx.data() + base + i * size_t(W);
-            for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
-                const int32_t u = M.col[size_t(j)];
-                if (stamp[size_t(u)] != mark) fail(LMS_ERR_STATE, "temporal-blocking plan: neighbour not staged");
-                row[j - M.row_ptr[v]] = uint16_t(slot[size_t(u)]);
-            }
-        }
-        P.lidx_ptr.push_back(P.lidx_ptr.back() + int64_t(rows));
-    };
-    std::vector<std::pair<int32_t, int32_t>> todo;
-    for (int64_t b0 = 0; b0 < n && P.fits; b0 += ts) {
-        todo.emplace_back(int32_t(b0), int32_t(std::min<int64_t>(n, b0 + ts)));
-        while (!todo.empty()) {
-            const auto [b, e] = todo.back();
-            todo.pop_back();
-            if (try_tile(b, e)) {
-                emit_tile(b, e);
-            } else if (e - b > 1) {  // halve; the left half goes first
-                const int32_t mid = b + (e - b) / 2;
-                todo.emplace_back(mid, e);
-                todo.emplace_back(b, mid);
-            } else {
-                P.fits = false;
-                break;
-            }
-        }
-    }
-    if (!P.fits) {
-        Mesh::TBPlan empty;
-        empty.ts = ts;
-        empty.k = k;
-        empty.u_cap = u_cap;
-        empty.l_cap = l_cap;
-        empty.fits = false;
-        P = std::move(empty);
-    } else {
-        P.tiles = int32_t(P.tile_ptr.size() - 1);
         // self-check: tiles cover the rows in order; each updated row's slots
         // name its CSR neighbours in order, inside the rows valid one sweep
         // earlier (own + one more ring)
         if (P.tile_ptr.back() != n) fail(LMS_ERR_STATE, "temporal-blocking plan: tiles do not cover the rows");
-        for (int32_t t = 0; t < P.tiles; ++t) {
-            const int32_t b = P.tile_ptr[size_t(t)], e = P.tile_ptr[size_t(t) + 1];
-            const int32_t *r = P.ring.data() + size_t(t) * size_t(k + 1);
-            const int64_t hb = P.halo_ptr[size_t(t)];
-            if (e <= b || r[0] != e - b || r[k] > l_cap || r[k - 1] > u_cap ||
-                P.halo_ptr[size_t(t) + 1] - hb != int64_t(r[k] - r[0]) ||
-                P.lidx_ptr[size_t(t) + 1] - P.lidx_ptr[size_t(t)] != int64_t(r[k - 1]))
-                fail(LMS_ERR_STATE, "temporal-blocking plan: tile counts");
-            auto global_of = [&](int32_t li) { return li < e - b ? b + li : P.halo[size_t(hb + li - (e - b))]; };
-            for (int32_t m = 0; m < k; ++m)
-                for (int32_t li = m == 0 ? 0 : r[m - 1]; li < r[m]; ++li) {
-                    const int32_t v = global_of(li);
-                    const uint16_t *row = P.lidx.data() + size_t(P.lidx_ptr[size_t(t)] + li) * size_t(W);
-                    const int32_t deg = M.row_ptr[v + 1] - M.row_ptr[v];
-                    for (int32_t q = 0; q < W; ++q) {
-                        if (q >= deg) {
-                            if (row[q] != 0xFFFF) fail(LMS_ERR_STATE, "temporal-blocking plan: padding slot in use");
-                            continue;
+        parallel_runs(P.tiles, host_threads(P.tiles), [&](int, int64_t first, int64_t last) {
+            for (int64_t t = first; t < last; ++t) {
+                const int32_t b = P.tile_ptr[size_t(t)], e = P.tile_ptr[size_t(t) + 1];
+                const int32_t *r = P.ring.data() + size_t(t) * size_t(k + 1);
+                const int64_t hb = P.halo_ptr[size_t(t)];
+                if (e <= b || r[0] != e - b || r[k] > l_cap || r[k - 1] > u_cap ||
+                    P.halo_ptr[size_t(t) + 1] - hb != int64_t(r[k] - r[0]) ||
+                    P.lidx_ptr[size_t(t) + 1] - P.lidx_ptr[size_t(t)] != int64_t(r[k - 1]))
+                    fail(LMS_ERR_STATE, "temporal-blocking plan: tile counts");
+                auto global_of = [&](int32_t li) { return li < e - b ? b + li : P.halo[size_t(hb + li - (e - b))]; };
+                for (int32_t m = 0; m < k; ++m)
+                    for (int32_t li = m == 0 ? 0 : r[m - 1]; li < r[m]; ++li) {
+                        const int32_t v = global_of(li);
+                        const uint16_t *row = P.lidx.data() + size_t(P.lidx_ptr[size_t(t)] + li) * size_t(W);
+                        const int32_t deg = M.row_ptr[v + 1] - M.row_ptr[v];
+                        for (int32_t q = 0; q < W; ++q) {
+                            if (q >= deg) {
+                                if (row[q] != 0xFFFF) fail(LMS_ERR_STATE, "temporal-blocking plan: padding slot in use");
+                                continue;
+                            }
+                            if (row[q] >= r[m + 1]) fail(LMS_ERR_STATE, "temporal-blocking plan: slot outside its ring");
+                            if (global_of(row[q]) != M.col[size_t(M.row_ptr[v] + q)])
+                                fail(LMS_ERR_STATE, "temporal-blocking plan: slot names the wrong vertex");
                         }
-                        if (row[q] >= r[m + 1]) fail(LMS_ERR_STATE, "temporal-blocking plan: slot outside its ring");
-                        if (global_of(row[q]) != M.col[size_t(M.row_ptr[v] + q)])
-                            fail(LMS_ERR_STATE, "temporal-blocking plan: slot names the wrong vertex");
                     }
-                }
-        }
+            }
+        });
     }
     P.version = M.version;
     M.tb_plans.push_back(std::move(P));

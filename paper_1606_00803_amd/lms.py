@@ -305,9 +305,9 @@ class Mesh:
         return out.value
 
     def sweep_config(self, precision="f64") -> str:
-        buf = ctypes.create_string_buffer(1024)
+        buf = ctypes.create_string_buffer(8192)
         p = FP64 if precision in ("f64", FP64) else FP32
-        _check(load().lms_sweep_config(self.handle, p, buf, 1024))
+        _check(load().lms_sweep_config(self.handle, p, buf, 8192))
         return buf.value.decode()
 
     def quality_batched(self, x, y) -> np.ndarray:
