@@ -31,13 +31,27 @@ namespace lms {
 // Device-side state of Algorithm 1's stopping rule.
 struct StopState {
     int32_t done;        // nonzero: stop; later sweeps in a captured chunk do nothing
-    int32_t iters;       // sweeps done so far
+    int32_t iters;       // sweeps done so far (fused path: the last state evaluated)
     int32_t stopped_by;  // lms_stop_reason
-    int32_t pad;
+    int32_t swept;       // fused path: state index held by the next pass's source copy
     double q0;
     double q_prev;       // Q_{k-1}
     double q_last;       // Q_k of the last evaluation
     double last_dq;
+    double q_const;      // fused path: sum of w_t q_t over triangles whose corners are all fixed
+    int32_t redo;        // fused path: sweeps from copy `src` that give the final state
+    int32_t src;         // fused path: 0 / 1, the working copy the final state comes from
+};
+
+// Arguments of the stopping rule (Section 5.1) for the fused path.
+struct StopArgs {
+    double inv_n;         // 1 / |V|
+    double tol, goal;
+    double q_prev_given;  // replaces Q_0 when use_q_prev
+    int32_t use_q_prev;
+    int32_t max_iters;
+    int32_t src_index;    // 0 / 1: the working copy this pass reads
+    int32_t pad;
 };
 
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
@@ -582,6 +596,10 @@ __device__ __forceinline__ void load_slot_words(const uint16_t *__restrict__ row
     }
 }
 
+__device__ __forceinline__ double tri_quality(double xa, double ya, double xb, double yb, double xc, double yc);
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double *s_red);
+
 // Temporally blocked Jacobi: k sweeps (Eq. 1, Algorithm 1) of the tile's
 // own rows in one pass over memory.  Tile t (rows tile_ptr[t] ..
 // tile_ptr[t+1]-1) stages its own rows and k halo
@@ -597,24 +615,60 @@ __device__ __forceinline__ void load_slot_words(const uint16_t *__restrict__ row
 // staging area fits the dynamic LDS it is launched with.  TS (nominal tile
 // size), KP (the plan's depth) and LCAP (its staging cap) name the variant
 // whose plan the kernel reads; the tiles themselves come from tile_ptr.
-template <typename T, int BS, int W, int R, int MAP, int TS, int KP, int LCAP>
+//
+// QUAL (the stopping rule, Section 5.1): the pass also evaluates the quality
+// (Section 3.2) of each state it starts a sweep from.  Before sweep j+1 the
+// own rows and ring 1 hold state s+j, and every triangle of the tile (those
+// whose smallest free corner is an own row) has its corners there; the
+// tile's sum of w_t q_t goes to qpart[j*gridDim.x + tile].  The depth comes
+// from the device state: k = min(KP, max_iters - swept), and a pass of depth
+// 0 (all sweeps done) evaluates its source state only.
+template <typename T, int BS, int W, int R, int MAP, int TS, int KP, int LCAP, bool QUAL>
 __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ tile_ptr,
                                                   const int32_t *__restrict__ ring, int32_t k,
                                                   const int64_t *__restrict__ halo_ptr,
                                                   const int32_t *__restrict__ halo,
                                                   const int64_t *__restrict__ lidx_ptr,
                                                   const uint16_t *__restrict__ lidx,
-                                                  const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst) {
+                                                  const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst,
+                                                  const int64_t *__restrict__ qtri_ptr,
+                                                  const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
+                                                  const StopState *__restrict__ st, int32_t max_iters) {
     static_assert(W % 4 == 0, "padded width must be a multiple of 4");
+    constexpr int QR = 2;     // triangle records per thread held in registers
+    constexpr int NRCP = 64;  // 1/c for triangle counts c = 1..NRCP from a table (the same division)
     extern __shared__ unsigned char lds_raw[];
+    __shared__ double s_red[BS / 64];
+    __shared__ double s_rcp[QUAL ? NRCP + 1 : 1];
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
+    if constexpr (QUAL) {
+        if (st->done) return;
+        k = min(KP, max_iters - st->swept);
+    }
     const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
     const int tid = int(threadIdx.x);
     const int32_t b = tile_ptr[tile];
     static_assert(KP >= 1 && KP <= 8 && TS > 0 && LCAP > 0, "plan shape");
     const int32_t *rc = ring + int64_t(tile) * (KP + 1);
-    const int32_t nown = rc[0], nload = rc[k], nupd = rc[k - 1];
+    const int32_t nown = rc[0], nload = rc[k > 0 ? k : 1], nupd = k > 0 ? rc[k - 1] : 0;
     const int64_t hb = halo_ptr[tile], lb = lidx_ptr[tile];
+    uint32_t qw[QUAL ? QR : 1][3];
+    int64_t qb = 0, qe = 0;
+    if constexpr (QUAL) {
+        for (int c = tid; c <= NRCP; c += BS) s_rcp[c] = c == 0 ? 0.0 : 1.0 / double(c);
+        qb = qtri_ptr[tile];
+        qe = qtri_ptr[tile + 1];
+#pragma unroll
+        for (int r = 0; r < QR; ++r) {
+            const int64_t t = qb + tid + BS * r;
+            qw[r][0] = qw[r][1] = qw[r][2] = 0u;  // count 0: no triangle
+            if (t < qe) {
+                qw[r][0] = qtri[3 * t];
+                qw[r][1] = qtri[3 * t + 1];
+                qw[r][2] = qtri[3 * t + 2];
+            }
+        }
+    }
     uint32_t wd[R][W / 2];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -653,7 +707,31 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             }
     }
     __syncthreads();
-    for (int32_t j = 1; j <= k; ++j) {
+    const int32_t passes = QUAL && k == 0 ? 1 : k;
+    for (int32_t j = 1; j <= passes; ++j) {
+        if constexpr (QUAL) {
+            // quality of state s+j-1: every triangle of the tile, from LDS
+            auto tri_term = [&](uint32_t w0, uint32_t w1, uint32_t w2) {
+                const vec2_t<T> pa = sp[w0 & 0xFFFFu], pb = sp[w0 >> 16], pc = sp[w1 & 0xFFFFu];
+                const double q = tri_quality(double(pa.x), double(pa.y), double(pb.x), double(pb.y), double(pc.x),
+                                             double(pc.y));
+                const uint32_t ca = w1 >> 16, cb = w2 & 0xFFFFu, cc = w2 >> 16;
+                const double ra = ca <= NRCP ? s_rcp[ca] : 1.0 / double(ca);
+                const double rb = cb <= NRCP ? s_rcp[cb] : 1.0 / double(cb);
+                const double rc = cc <= NRCP ? s_rcp[cc] : 1.0 / double(cc);
+                return q * (ra + rb + rc);
+            };
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < QR; ++r)
+                if ((qw[r][1] >> 16) != 0u) acc += tri_term(qw[r][0], qw[r][1], qw[r][2]);
+            for (int64_t t = qb + QR * BS + tid; t < qe; t += BS)
+                acc += tri_term(qtri[3 * t], qtri[3 * t + 1], qtri[3 * t + 2]);
+            const double sum = block_sum<BS>(acc, s_red);
+            if (tid == 0) qpart[int64_t(j - 1) * gridDim.x + tile] = sum;
+            __syncthreads();  // s_red is reused by the next state's sum
+            if (k == 0) break;
+        }
         const int32_t m = rc[k - j];  // rows updated by this sweep
         vec2_t<T> o[R];
         bool w[R];
@@ -986,13 +1064,110 @@ __global__ __launch_bounds__(256) void k_stop(const double *__restrict__ partial
     st->q_prev = Q;
 }
 
+// The stopping rule for the fused path, after each quality-fused pass (one
+// workgroup): apply the rule to each state the pass evaluated (s, s+1, ...,
+// one per sweep it started, or s alone for a depth-0 pass), in order, from
+// the tiles' partial sums plus the all-fixed constant.  On a stop at state
+// s+j the final state is j sweeps past the pass's source copy: record both;
+// else advance `swept` past the pass.  Each thread sums a fixed set of tiles
+// (four independent loads in flight), so the order is the same every run.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_stop_tb(const double *__restrict__ qpart, int32_t tiles, int32_t kp,
+                                                StopState *st, StopArgs a) {
+    __shared__ double s_red_arr[NT / 64];
+    __shared__ int stop_flag;
+    double *s_red = s_red_arr;
+    int *stop = &stop_flag;
+    if (st->done) return;
+    const int32_t s0 = st->swept;
+    const int32_t k = min(kp, a.max_iters - s0);
+    const int32_t nq = k > 0 ? k : 1;
+    if (threadIdx.x == 0) *stop = 0;
+    for (int32_t j = 0; j < nq; ++j) {
+        __syncthreads();
+        const double *p = qpart + int64_t(j) * tiles;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t i0 = int32_t(threadIdx.x); i0 < tiles; i0 += 4 * NT) {
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = i0 + q * NT < tiles ? p[i0 + q * NT] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += v[q];
+        }
+        const double sum = block_sum<NT>((acc[0] + acc[1]) + (acc[2] + acc[3]), s_red);
+        if (threadIdx.x == 0) {
+            const double Q = (sum + st->q_const) * a.inv_n;
+            const int32_t it = s0 + j;
+            bool done = false;
+            if (it == 0) {
+                const double q0 = a.use_q_prev ? a.q_prev_given : Q;
+                st->q0 = q0;
+                st->q_prev = q0;
+                st->q_last = q0;
+                st->iters = 0;
+                st->last_dq = __builtin_nan("");
+                if (q0 >= a.goal) {
+                    st->stopped_by = LMS_STOP_GOAL;
+                    done = true;
+                } else if (a.max_iters <= 0) {
+                    st->stopped_by = LMS_STOP_MAX_ITERS;
+                    done = true;
+                }
+            } else {
+                const double dq = Q - st->q_prev;
+                st->iters = it;
+                st->q_last = Q;
+                st->last_dq = dq;
+                if (Q >= a.goal) {
+                    st->stopped_by = LMS_STOP_GOAL;
+                    done = true;
+                } else if (dq < a.tol) {
+                    st->stopped_by = LMS_STOP_TOL;
+                    done = true;
+                } else if (it >= a.max_iters) {
+                    st->stopped_by = LMS_STOP_MAX_ITERS;
+                    done = true;
+                }
+                st->q_prev = Q;
+            }
+            if (done) {
+                st->redo = j;
+                st->src = a.src_index;
+                st->done = 1;
+                *stop = 1;
+            }
+        }
+        __syncthreads();
+        if (*stop) return;
+    }
+    if (threadIdx.x == 0) st->swept = s0 + k;
+}
+
+// Sum of w_t q_t over the triangles whose corners are all fixed (their
+// quality never changes during smoothing) into st->q_const.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qconst(const int32_t *__restrict__ ids, const double *__restrict__ w,
+                                                int64_t cnt, const vec2_t<T> *__restrict__ xy, StopState *st) {
+    __shared__ double s_red[4];
+    double acc = 0.0;
+    for (int64_t t = threadIdx.x; t < cnt; t += 256) {
+        const vec2_t<T> a = xy[ids[3 * t]], b = xy[ids[3 * t + 1]], c = xy[ids[3 * t + 2]];
+        acc += tri_quality(double(a.x), double(a.y), double(b.x), double(b.y), double(c.x), double(c.y)) * w[t];
+    }
+    const double sum = block_sum<256>(acc, s_red);
+    if (threadIdx.x == 0) st->q_const = sum;
+}
+
 __global__ void k_stop_reset(StopState *st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->done = 0;
         st->iters = 0;
         st->stopped_by = LMS_STOP_MAX_ITERS;
-        st->pad = 0;
+        st->swept = 0;
         st->q0 = st->q_prev = st->q_last = st->last_dq = __builtin_nan("");
+        st->q_const = 0.0;
+        st->redo = 0;
+        st->src = 0;
     }
 }
 
@@ -1095,6 +1270,14 @@ struct DeviceState {
         int32_t *tile_ptr = nullptr, *ring = nullptr, *halo = nullptr;
         int64_t *halo_ptr = nullptr, *lidx_ptr = nullptr;
         uint16_t *lidx = nullptr;
+        // quality-fused form (uploaded on first use under the stopping rule)
+        bool q_ready = false, q_fits = false;
+        int64_t *qtri_ptr = nullptr;
+        uint32_t *qtri = nullptr;
+        double *qpart = nullptr;  // k x tiles partial sums
+        int32_t *qc_ids = nullptr;
+        double *qc_w = nullptr;
+        int64_t n_qc = 0;
     };
     std::vector<TBDev> tbs;      // uploaded temporal-blocking plans of the current version
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
@@ -1119,6 +1302,7 @@ struct DeviceState {
     int sweep_cfg[2] = {-1, -1};     // separate-array sweep variant per precision, -1 = not tuned
     int smooth_cfg[2] = {-1, -1};    // variant lms_smooth uses (may sweep the interleaved copy)
     int tb_cfg[2] = {-1, -1};        // temporally blocked variant for fixed-K Jacobi, -1 = none
+    int tb_best[2] = {-1, -1};       // fastest temporally blocked variant (the stopping rule's fused pass)
     // end of the handle's last device call: a call on another stream waits
     // for it (the handle's buffers are shared between calls), and nothing the
     // calls may use is freed before it
@@ -1228,6 +1412,7 @@ DeviceState &ensure_device(Mesh &M) {
         d->sweep_cfg[0] = d->sweep_cfg[1] = -1;  // a new ordering is tuned afresh
         d->smooth_cfg[0] = d->smooth_cfg[1] = -1;
         d->tb_cfg[0] = d->tb_cfg[1] = -1;
+        d->tb_best[0] = d->tb_best[1] = -1;
         d->version = M.version;
     }
     return *d;
@@ -1549,6 +1734,29 @@ const DeviceState::TBDev &ensure_tb(DeviceState &d, Mesh &M, const TBShape &t) {
     return d.tbs.back();
 }
 
+// The quality-fused form of a temporally blocked plan (false when some
+// vertex lies in more than 65535 triangles).
+bool ensure_tbq(DeviceState &d, Mesh &M, const TBShape &t) {
+    DeviceState::TBDev *h = const_cast<DeviceState::TBDev *>(find_tb(d, t));
+    if (!h || !h->fits) fail(LMS_ERR_STATE, "quality-fused pass without its tile plan");
+    if (h->q_ready) return h->q_fits;
+    Mesh::TBPlan *P = nullptr;
+    for (auto &p : M.tb_plans)
+        if (p.ts == t.ts && p.k == t.k && p.u_cap == t.bs * t.r && p.l_cap == t.lcap && p.version == M.version) P = &p;
+    if (!P) fail(LMS_ERR_STATE, "tile plan missing on the host");
+    tb_quality_plan(M, *P);
+    h->q_ready = true;
+    h->q_fits = P->q_fits;
+    if (!h->q_fits) return false;
+    h->qtri_ptr = upload(&d, P->qtri_ptr);
+    h->qtri = upload(&d, P->qtri);
+    h->qc_ids = upload(&d, P->qc_ids);
+    h->qc_w = upload(&d, P->qc_w);
+    h->n_qc = int64_t(P->qc_w.size());
+    h->qpart = upload(&d, std::vector<double>(size_t(t.k) * size_t(std::max(h->tiles, 1)), 0.0));
+    return true;
+}
+
 int sweep_config_tile(int cfg);  // tile size of a halo-staged variant, 0 otherwise
 
 // Whether variant cfg can run on this mesh in precision T (builds the tile
@@ -1602,13 +1810,19 @@ void launch_sweep_cfg(int cfg, const DeviceState &d, const Mesh &M, const T *sx,
 }
 
 // k (1 <= k <= the variant's depth) Jacobi sweeps src -> dst in one pass of
-// a temporally blocked variant.  dst's fixed rows are not written.
+// a temporally blocked variant.  dst's fixed rows are not written.  With
+// `qual`, the pass is the quality-fused form: its depth comes from the
+// device state (k is ignored) and it writes the tiles' quality sums.
 template <typename T>
 void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst, int32_t k,
-                   hipStream_t s) {
+                   hipStream_t s, bool qual = false, int32_t max_iters = 0) {
     const TBShape t = tb_shape(cfg);
     const DeviceState::TBDev *h = find_tb(d, t);
     if (!h || !h->fits || M.ell_w != t.w) fail(LMS_ERR_STATE, "temporally blocked variant launched without its plan");
+    if (qual) {
+        if (!h->q_ready || !h->q_fits) fail(LMS_ERR_STATE, "quality-fused pass without its triangle plan");
+        k = t.k;
+    }
     if (k < 1 || k > t.k) fail(LMS_ERR_STATE, "temporally blocked pass deeper than its plan");
     if (h->u_max > t.bs * t.r || size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024)
         fail(LMS_ERR_STATE, "temporally blocked plan does not fit the variant");
@@ -1617,8 +1831,14 @@ void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T>
     switch (cfg) {
 #define TB(id, bs, w, r, map, ts, kk, lcap)                                                                    \
     case id:                                                                                                   \
-        k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap><<<h->tiles, bs, lds, s>>>(                               \
-            h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst);                     \
+        if (qual)                                                                                              \
+            k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, true><<<h->tiles, bs, lds, s>>>(                       \
+                h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, h->qtri_ptr,     \
+                h->qtri, h->qpart, d.st, max_iters);                                                           \
+        else                                                                                                   \
+            k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, false><<<h->tiles, bs, lds, s>>>(                      \
+                h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, nullptr,        \
+                nullptr, nullptr, nullptr, 0);                                                                 \
         break;
         LMS_TB_CONFIGS(TB)
 #undef TB
@@ -1702,14 +1922,14 @@ template <typename T>
 void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy, hipStream_t s) {
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (d.sweep_cfg[pi] >= 0) return;
-    d.tb_cfg[pi] = -1;
+    d.tb_cfg[pi] = d.tb_best[pi] = -1;
     if (const char *f = std::getenv("LMS_SWEEP_CONFIG")) {
         const int c = std::atoi(f);
         if (c < 0 || c >= kNumAllConfigs) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG out of range");
         if (!sweep_config_usable<T>(c, d, M)) fail(LMS_ERR_ARG, "LMS_SWEEP_CONFIG names a variant this mesh cannot use");
         d.sweep_cfg[pi] = sweep_config_packed(c) ? kDefaultSweepConfig : c;
         d.smooth_cfg[pi] = is_tb_config(c) ? kDefaultSweepConfig : c;
-        if (is_tb_config(c)) d.tb_cfg[pi] = c;
+        if (is_tb_config(c)) d.tb_cfg[pi] = d.tb_best[pi] = c;
         return;
     }
     if (!env_flag("LMS_AUTOTUNE", true)) {
@@ -1780,6 +2000,7 @@ void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
     d.sweep_cfg[pi] = best;
     d.smooth_cfg[pi] = best_all;
     d.tb_cfg[pi] = best_tb >= 0 && best_tb_ms < best_all_ms ? best_tb : -1;
+    d.tb_best[pi] = best_tb;
     if (env_flag("LMS_VERBOSE", false)) {
         std::fprintf(stderr,
                      "[lms] sweep autotune (%s, n=%d): %s, %.2f us (separate arrays: %s, %.2f us; "
@@ -1964,6 +2185,20 @@ void launch_small_meshes(DeviceState &d, const Mesh &M, vec2_t<T> *A, vec2_t<T> 
     launch_check();
 }
 
+// Passes per captured chunk of the quality-fused stopping rule (even, so that
+// every chunk starts from copy A).
+constexpr int kFusedChunk = 8;
+
+// The temporally blocked variant whose quality-fused form runs the stopping
+// rule, or -1 (then sweep and quality pass run separately).
+template <typename T>
+int fused_stop_cfg(DeviceState &d, Mesh &M) {
+    const int pi = sizeof(T) == 8 ? 0 : 1;
+    const int c = d.tb_best[pi];
+    if (c < 0 || !env_flag("LMS_FUSED_QUALITY", true)) return -1;
+    return ensure_tbq(d, M, tb_shape(c)) ? c : -1;
+}
+
 // lms_smooth on the interleaved working copies: pack P_0 into both copies,
 // sweep back and forth between them (graph-captured), unpack the last one.
 template <typename T>
@@ -2025,6 +2260,49 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         in_b = !colour && K % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
+    } else if (const int fq = colour ? -1 : fused_stop_cfg<T>(d, M); fq >= 0) {
+        // stopping rule with the quality fused into the sweep passes: each
+        // pass evaluates the states it sweeps from; a stop inside a pass is
+        // reached again from the pass's source copy
+        const TBShape t = tb_shape(fq);
+        const DeviceState::TBDev *h = find_tb(d, t);
+        k_stop_reset<<<1, 64, 0, s>>>(d.st);
+        k_qconst<T><<<1, 256, 0, s>>>(h->qc_ids, h->qc_w, h->n_qc, A, d.st);
+        launch_check();
+        const bool use_prev = !std::isnan(o.q_prev);
+        const std::string key = "stopq|" + base + "|tb" + std::to_string(fq) + "|" + dbl_key(o.tol) + "|" +
+                                dbl_key(o.goal) + "|" + std::to_string(o.max_iters);
+        // every chunk advances at least kFusedChunk*depth sweeps or ends the run
+        const int64_t max_chunks = (int64_t(o.max_iters) + 1) / (int64_t(kFusedChunk) * t.k) + 2;
+        for (int64_t chunk = 0;; ++chunk) {
+            HIP_CHECK(hipMemcpyAsync(d.h_st, d.st, sizeof(StopState), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            if (d.h_st->done) break;
+            if (chunk > max_chunks) fail(LMS_ERR_STATE, "the fused stopping rule made no progress");
+            run_maybe_graph(d, key, s, [&](hipStream_t cs) {
+                for (int q = 0; q < kFusedChunk; ++q) {
+                    StopArgs sa{};
+                    sa.inv_n = 1.0 / double(M.n);
+                    sa.tol = o.tol;
+                    sa.goal = o.goal;
+                    sa.q_prev_given = use_prev ? o.q_prev : 0.0;
+                    sa.use_q_prev = use_prev ? 1 : 0;
+                    sa.max_iters = o.max_iters;
+                    sa.src_index = q % 2;
+                    launch_tb_cfg<T>(fq, d, M, q % 2 == 0 ? A : B, q % 2 == 0 ? B : A, 0, cs, true, o.max_iters);
+                    k_stop_tb<1024><<<1, 1024, 0, cs>>>(h->qpart, h->tiles, t.k, d.st, sa);
+                }
+            });
+        }
+        const StopState hs = *d.h_st;
+        vec2_t<T> *fsrc = hs.src == 0 ? A : B, *fother = hs.src == 0 ? B : A;
+        if (hs.redo > 0) launch_tb_cfg<T>(fq, d, M, fsrc, fother, hs.redo, s);
+        in_b = (hs.redo > 0 ? fother : fsrc) == B;
+        iters = hs.iters;
+        r.stopped_by = hs.stopped_by;
+        r.q0 = hs.q0;
+        r.q_final = hs.q_last;
+        r.last_dq = hs.last_dq;
     } else {
         k_stop_reset<<<1, 64, 0, s>>>(d.st);
         launch_quality<T>(d, M, nullptr, nullptr, nullptr, nullptr, s, A);
@@ -2073,7 +2351,8 @@ void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precisi
         }
         tune_sweep<T>(d, M, x, y, tx, ty, s);
         const int pi = sizeof(T) == 8 ? 0 : 1;
-        if (sweep_config_packed(d.smooth_cfg[pi]) || (!o.check_quality && d.tb_cfg[pi] >= 0)) {
+        if (sweep_config_packed(d.smooth_cfg[pi]) || (!o.check_quality && d.tb_cfg[pi] >= 0) ||
+            (o.check_quality && fused_stop_cfg<T>(d, M) >= 0)) {
             smooth_packed<T>(M, d, x, y, p, sch, o, s, r);
             return;
         }

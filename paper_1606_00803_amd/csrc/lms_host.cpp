@@ -768,4 +768,83 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
     return M.tb_plans.back();
 }
 
+void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
+    if (P.q_built) return;
+    if (!P.fits || P.version != M.version) fail(LMS_ERR_STATE, "quality plan of a stale or unusable tile plan");
+    const int64_t T = M.T;
+    const int32_t k = P.k;
+    P.q_built = true;
+    P.q_fits = false;
+    for (int32_t v = 0; v < M.n; ++v)
+        if (M.tcount0[size_t(v)] > 0xFFFF) return;  // counts do not fit 16 bits
+    // owning tile and record of every triangle with a free corner (-1: all fixed)
+    std::vector<int32_t> owner(size_t(T), -1);
+    std::vector<uint32_t> rec(size_t(3) * size_t(T), 0u);
+    parallel_runs(T, host_threads(T / 256), [&](int, int64_t first, int64_t last) {
+        for (int64_t t = first; t < last; ++t) {
+            const int32_t c3[3] = {M.ta[size_t(t)], M.tb[size_t(t)], M.tc[size_t(t)]};
+            int32_t own = -1;
+            for (int32_t v : c3)
+                if (!M.fixed[size_t(v)] && (own < 0 || v < own)) own = v;
+            if (own < 0) continue;
+            const int32_t tile =
+                int32_t(std::upper_bound(P.tile_ptr.begin(), P.tile_ptr.end(), own) - P.tile_ptr.begin()) - 1;
+            const int32_t b = P.tile_ptr[size_t(tile)], e = P.tile_ptr[size_t(tile) + 1];
+            const int32_t *r = P.ring.data() + size_t(tile) * size_t(k + 1);
+            const int32_t *h1 = P.halo.data() + P.halo_ptr[size_t(tile)];
+            const int32_t n1 = r[1] - r[0];
+            uint32_t slot[3], cnt[3];
+            for (int q = 0; q < 3; ++q) {
+                const int32_t v = c3[q];
+                if (v >= b && v < e) {
+                    slot[q] = uint32_t(v - b);
+                } else {
+                    const int32_t *it = std::lower_bound(h1, h1 + n1, v);
+                    if (it == h1 + n1 || *it != v) fail(LMS_ERR_STATE, "quality plan: corner not staged");
+                    slot[q] = uint32_t(r[0] + (it - h1));
+                }
+                cnt[q] = uint32_t(M.tcount0[size_t(M.new2old[size_t(v)])]);
+            }
+            owner[size_t(t)] = tile;
+            rec[size_t(3 * t)] = slot[0] | (slot[1] << 16);
+            rec[size_t(3 * t + 1)] = slot[2] | (cnt[0] << 16);
+            rec[size_t(3 * t + 2)] = cnt[1] | (cnt[2] << 16);
+        }
+    });
+    // group by tile (stable: ascending triangle index inside a tile)
+    P.qtri_ptr.assign(size_t(P.tiles) + 1, 0);
+    P.qc_ids.clear();
+    P.qc_w.clear();
+    for (int64_t t = 0; t < T; ++t) {
+        if (owner[size_t(t)] >= 0) {
+            P.qtri_ptr[size_t(owner[size_t(t)]) + 1]++;
+        } else {
+            const int32_t a = M.ta[size_t(t)], bb = M.tb[size_t(t)], c = M.tc[size_t(t)];
+            P.qc_ids.insert(P.qc_ids.end(), {a, bb, c});
+            P.qc_w.push_back(M.tw[size_t(t)]);
+        }
+    }
+    for (int32_t i = 0; i < P.tiles; ++i) P.qtri_ptr[size_t(i) + 1] += P.qtri_ptr[size_t(i)];
+    resize_or_fail(P.qtri, size_t(3) * size_t(P.qtri_ptr.back()));
+    std::vector<int64_t> fill(P.qtri_ptr.begin(), P.qtri_ptr.end() - 1);
+    for (int64_t t = 0; t < T; ++t) {
+        const int32_t o = owner[size_t(t)];
+        if (o < 0) continue;
+        const int64_t at = fill[size_t(o)]++;
+        for (int q = 0; q < 3; ++q) P.qtri[size_t(3 * at + q)] = rec[size_t(3 * t + q)];
+    }
+    // self-check: every triangle counted once, its slots inside own + ring 1
+    if (P.qtri_ptr.back() + int64_t(P.qc_w.size()) != T) fail(LMS_ERR_STATE, "quality plan: triangle count");
+    for (int32_t i = 0; i < P.tiles; ++i) {
+        const int32_t *r = P.ring.data() + size_t(i) * size_t(k + 1);
+        for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t) {
+            const uint32_t w0 = P.qtri[size_t(3 * t)], w1 = P.qtri[size_t(3 * t + 1)], w2 = P.qtri[size_t(3 * t + 2)];
+            if ((w0 & 0xFFFFu) >= uint32_t(r[1]) || (w0 >> 16) >= uint32_t(r[1]) || (w1 & 0xFFFFu) >= uint32_t(r[1]) ||
+                (w1 >> 16) == 0 || (w2 & 0xFFFFu) == 0 || (w2 >> 16) == 0)
+                fail(LMS_ERR_STATE, "quality plan: record out of range");
+        }
+    }
+    P.q_fits = true;
+}
+
 }  // namespace lms

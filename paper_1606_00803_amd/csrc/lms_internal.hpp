@@ -109,6 +109,18 @@ struct Mesh {
         std::vector<int32_t> halo;      // per tile: rings 1..k
         std::vector<int64_t> lidx_ptr;  // tiles+1, in rows of ell_w slots
         std::vector<uint16_t> lidx;
+        // Quality of each staged state (filled by tb_quality_plan): every
+        // triangle with a free corner belongs to the tile that owns its
+        // smallest free corner, whose neighbours (the other two corners) are
+        // staged in its own rows or ring 1.  Record: 3 words, slots a | b<<16,
+        // c | |T(a)|<<16, |T(b)| | |T(c)|<<16 (corners in the order of ta,
+        // tb, tc).  Triangles whose corners are all fixed never change; they
+        // are listed apart in current labels with their weights.
+        bool q_built = false, q_fits = false;
+        std::vector<int64_t> qtri_ptr;  // tiles+1, in triangles
+        std::vector<uint32_t> qtri;     // 3 words per triangle
+        std::vector<int32_t> qc_ids;    // 3 per all-fixed triangle
+        std::vector<double> qc_w;       // its weight 1/|T(a)| + 1/|T(b)| + 1/|T(c)|
         uint64_t version = ~uint64_t(0);
     };
     std::vector<TBPlan> tb_plans;
@@ -130,6 +142,7 @@ std::vector<int32_t> order_random(const Mesh &M, uint64_t seed);
 void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old);
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap);
+void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
 
 // ---- device runtime (lms_device.hip) ----
 void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,

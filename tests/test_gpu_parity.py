@@ -557,3 +557,43 @@ def test_calls_on_two_streams_are_ordered_by_the_handle():
     torch.cuda.synchronize()
     for x, y in ((xa, ya), (xb, yb)):
         assert torch.equal(x, rx) and torch.equal(y, ry)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("cfg", [45, 51, 54])        # width 8, depths 2, 3 and 4
+def test_fused_quality_stopping_rule_matches_separate_passes(prec, cfg):
+    # the stopping rule with the quality evaluated inside the temporally
+    # blocked passes (a stop inside a pass reached again from its source copy)
+    # against sweep + separate quality pass: same stop sweep, reason and bits
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    dt = torch.float64 if prec == "f64" else torch.float32
+    m = meshgen.jittered_grid(150, 131, seed=42, land_fraction=0.3)
+    ref = osm.smooth(oracle_topology(m), m.x, m.y, max_iters=2000)
+    mid_goal = ref.q_history[7] - 1e-12                  # reached at sweep 7
+    cases = [dict(max_iters=2000), dict(max_iters=0), dict(max_iters=1), dict(max_iters=2),
+             dict(max_iters=3), dict(max_iters=5), dict(max_iters=2000, goal=ref.q0 - 1e-9),
+             dict(max_iters=2000, goal=mid_goal), dict(max_iters=2000, q_prev=ref.q_history[3])]
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    try:
+        for kw in cases:
+            out = {}
+            for fused in ("1", "0"):
+                os.environ["LMS_FUSED_QUALITY"] = fused
+                os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
+                x, y, r, _ = run_library(m, "rdr", kw["max_iters"], dtype=dt, M=M, check_quality=True,
+                                         **{k: v for k, v in kw.items() if k != "max_iters"})
+                out[fused] = (x, y, r)
+            (xf, yf, rf), (xs, ys, rs) = out["1"], out["0"]
+            assert rf["iters"] == rs["iters"] and rf["stopped_by"] == rs["stopped_by"], (kw, rf, rs)
+            assert np.array_equal(xf, xs) and np.array_equal(yf, ys), kw
+            for key in ("q0", "q_final", "last_dq"):
+                a, b = rf[key], rs[key]
+                assert (math.isnan(a) and math.isnan(b)) or abs(a - b) <= 1e-12, (kw, key, a, b)
+            if kw == dict(max_iters=2000) and prec == "f64":
+                assert rf["iters"] == ref.iters and rf["stopped_by"] == "tol"
+            if "goal" in kw and kw["goal"] == mid_goal and prec == "f64":
+                assert rf["iters"] == 7 and rf["stopped_by"] == "goal"
+    finally:
+        os.environ.pop("LMS_FUSED_QUALITY", None)
+        os.environ.pop("LMS_SWEEP_CONFIG", None)
