@@ -237,6 +237,34 @@ lms_status lms_get_order(lms_mesh_t m, int32_t *new2old);
  * coordinates (the qualities RDR sorts by): q host float64[n] out. */
 lms_status lms_host_vertex_quality(lms_mesh_t m, const double *x, const double *y, double *q);
 
+/* Locality of the current ordering (Section 2, reuse distance and cache
+ * misses; the quantiles of Table 2), computed on the host.  The trace is one
+ * Jacobi sweep in storage order: each free vertex in ascending current label,
+ * then its neighbours in ascending current label; items are current labels.
+ * The reuse distance of an access is the number of distinct items accessed
+ * since the previous access to the same item (first accesses are cold and
+ * have none).  For the GPU, lines_per_wave is the mean number of distinct
+ * cache lines of line_bytes bytes (records of record_bytes bytes stored by
+ * current label) that the neighbour reads of 64 consecutive rows touch, over
+ * the waves that hold a free row.
+ *   fractions  host double[nfrac] in [0, 1]
+ *   quantiles  host int64[nfrac] out: for each fraction X, the smallest d
+ *              such that at least a fraction X of the distances are <= d
+ *   stats      host out
+ * Fails with LMS_ERR_ARG for a fraction outside [0, 1] or non-positive sizes,
+ * and LMS_ERR_STATE when the trace exceeds 2^31 accesses. */
+typedef struct lms_reuse_stats {
+    int64_t accesses;           /* trace length */
+    int64_t cold;               /* first accesses */
+    int64_t max;                /* largest reuse distance */
+    double mean;                /* mean reuse distance of the other accesses */
+    double lines_per_wave;
+    int64_t max_lines_per_wave;
+} lms_reuse_stats;
+
+lms_status lms_reuse_profile(lms_mesh_t m, const double *fractions, int32_t nfrac, int64_t *quantiles,
+                             int32_t line_bytes, int32_t record_bytes, lms_reuse_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

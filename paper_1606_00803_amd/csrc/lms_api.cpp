@@ -234,4 +234,12 @@ lms_status lms_host_vertex_quality(lms_mesh_t m, const double *x, const double *
     });
 }
 
+lms_status lms_reuse_profile(lms_mesh_t m, const double *fractions, int32_t nfrac, int64_t *quantiles,
+                             int32_t line_bytes, int32_t record_bytes, lms_reuse_stats *stats) {
+    return guarded([&] {
+        if (!stats) lms::fail(LMS_ERR_ARG, "null stats");
+        lms::reuse_profile(mesh_of(m), fractions, nfrac, quantiles, line_bytes, record_bytes, *stats);
+    });
+}
+
 }  // extern "C"

@@ -5,6 +5,7 @@
 // computed with exactly the IEEE operations written here, so any other code
 // performing the same operations in the same order gets the same bits.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -571,6 +572,13 @@ class SlotMap {
     size_t mask_ = 0;
 };
 
+// A temporal-blocking plan is given up (the variant is unusable) once the
+// tiles built so far (at least a sixteenth of the rows, over all workers)
+// stage more than this many rows per own row: sweeping the halo rings would
+// cost far more than it saves (a random ordering stages dozens; RDR about 3
+// at depth 2).
+constexpr int64_t kTBMaxStagedPerRow = 6;
+
 // The tiles one worker builds for a run of nominal tiles.
 struct TBPart {
     bool fits = true;
@@ -618,6 +626,9 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
     const int64_t nominal = (int64_t(n) + ts - 1) / ts;
     const int workers = host_threads(nominal);
     std::vector<TBPart> parts(static_cast<size_t>(workers));
+    std::atomic<bool> give_up{false};
+    std::atomic<int64_t> all_own{0}, all_staged{0};
+    const int64_t sample = std::max<int64_t>(4096, int64_t(n) / 16);
     parallel_runs(nominal, workers, [&](int w, int64_t first, int64_t last) {
         TBPart &out = parts[size_t(w)];
         SlotMap slots(size_t(l_cap) + size_t(W) + 1);
@@ -674,18 +685,30 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
         };
         std::vector<std::pair<int32_t, int32_t>> todo;
         for (int64_t t = first; t < last && out.fits; ++t) {
+            if (give_up.load(std::memory_order_relaxed)) {
+                out.fits = false;
+                break;
+            }
             todo.emplace_back(int32_t(t * ts), int32_t(std::min<int64_t>(n, (t + 1) * ts)));
             while (!todo.empty()) {
                 const auto [b, e] = todo.back();
                 todo.pop_back();
                 if (try_tile(b, e)) {
                     emit_tile(b, e);
+                    const int64_t own = all_own.fetch_add(rc[0]) + rc[0];
+                    const int64_t staged = all_staged.fetch_add(rc[k]) + rc[k];
+                    if (own > sample && staged > kTBMaxStagedPerRow * own) {
+                        out.fits = false;
+                        give_up.store(true, std::memory_order_relaxed);
+                        break;
+                    }
                 } else if (e - b > 1) {  // halve; the left half goes first
                     const int32_t mid = b + (e - b) / 2;
                     todo.emplace_back(mid, e);
                     todo.emplace_back(b, mid);
                 } else {
                     out.fits = false;
+                    give_up.store(true, std::memory_order_relaxed);
                     break;
                 }
             }
@@ -845,6 +868,94 @@ void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
         }
     }
     P.q_fits = true;
+}
+
+// Locality profile of the current ordering: reuse distances of the sweep's
+// access trace (a Fenwick tree over trace positions marks each item's last
+// access; the distinct items since then are the marks after it), exact
+// quantiles from their histogram, and cache-line spans per wavefront.
+void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,
+                   int32_t record_bytes, lms_reuse_stats &out) {
+    if (nfrac < 0 || (nfrac > 0 && (!fractions || !quantiles)) || line_bytes <= 0 || record_bytes <= 0)
+        fail(LMS_ERR_ARG, "reuse profile: bad fractions or sizes");
+    for (int32_t i = 0; i < nfrac; ++i)
+        if (!(fractions[i] >= 0.0 && fractions[i] <= 1.0)) fail(LMS_ERR_ARG, "reuse profile: fraction outside [0, 1]");
+    const int32_t n = M.n;
+    int64_t L = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (!M.fixed[size_t(v)]) L += 1 + (M.row_ptr[v + 1] - M.row_ptr[v]);
+    if (L >= (int64_t(1) << 31)) fail(LMS_ERR_STATE, "reuse profile: trace too long");
+    std::vector<int32_t> fen(size_t(L) + 1, 0);  // 1-based Fenwick tree over trace positions
+    auto add = [&](int64_t i, int32_t d) {
+        for (++i; i <= L; i += i & -i) fen[size_t(i)] += d;
+    };
+    auto prefix = [&](int64_t i) {  // marks at positions [0, i)
+        int64_t acc = 0;
+        for (; i > 0; i -= i & -i) acc += fen[size_t(i)];
+        return acc;
+    };
+    std::vector<int64_t> last(size_t(n), -1);
+    std::vector<int64_t> hist(size_t(n) + 1, 0);
+    int64_t t = 0, cold = 0, dmax = 0;
+    double dsum = 0.0;
+    auto access = [&](int32_t x) {
+        const int64_t p = last[size_t(x)];
+        if (p < 0) {
+            ++cold;
+        } else {
+            const int64_t d = prefix(t) - prefix(p + 1);
+            hist[size_t(d)]++;
+            dsum += double(d);
+            dmax = std::max(dmax, d);
+            add(p, -1);
+        }
+        add(t, 1);
+        last[size_t(x)] = t;
+        ++t;
+    };
+    for (int32_t v = 0; v < n; ++v) {
+        if (M.fixed[size_t(v)]) continue;
+        access(v);
+        for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) access(M.col[size_t(j)]);
+    }
+    const int64_t total = L - cold;
+    for (int32_t i = 0; i < nfrac; ++i) {
+        int64_t q = 0;
+        if (total > 0) {
+            const int64_t need = std::max<int64_t>(1, int64_t(std::ceil(fractions[i] * double(total) - 1e-12)));
+            int64_t cum = 0;
+            for (q = 0; q <= n; ++q) {
+                cum += hist[size_t(q)];
+                if (cum >= need) break;
+            }
+        }
+        quantiles[i] = q;
+    }
+    // cache lines touched by the neighbour reads of each wavefront of 64 rows
+    std::vector<int64_t> lines;
+    int64_t waves = 0, span_sum = 0, span_max = 0;
+    for (int32_t w0 = 0; w0 < n; w0 += 64) {
+        lines.clear();
+        bool any_free = false;
+        for (int32_t v = w0; v < std::min(n, w0 + 64); ++v) {
+            if (M.fixed[size_t(v)]) continue;
+            any_free = true;
+            for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j)
+                lines.push_back(int64_t(M.col[size_t(j)]) * record_bytes / line_bytes);
+        }
+        if (!any_free) continue;
+        std::sort(lines.begin(), lines.end());
+        const int64_t span = int64_t(std::unique(lines.begin(), lines.end()) - lines.begin());
+        ++waves;
+        span_sum += span;
+        span_max = std::max(span_max, span);
+    }
+    out.accesses = L;
+    out.cold = cold;
+    out.max = dmax;
+    out.mean = total > 0 ? dsum / double(total) : 0.0;
+    out.lines_per_wave = waves > 0 ? double(span_sum) / double(waves) : 0.0;
+    out.max_lines_per_wave = span_max;
 }
 
 }  // namespace lms

@@ -143,6 +143,8 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old);
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap);
 void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
+void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,
+                   int32_t record_bytes, lms_reuse_stats &out);
 
 // ---- device runtime (lms_device.hip) ----
 void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,

@@ -47,6 +47,12 @@ class Result(ctypes.Structure):
                 ("q0", ctypes.c_double), ("q_final", ctypes.c_double), ("last_dq", ctypes.c_double)]
 
 
+class ReuseStats(ctypes.Structure):
+    _fields_ = [("accesses", ctypes.c_int64), ("cold", ctypes.c_int64), ("max", ctypes.c_int64),
+                ("mean", ctypes.c_double), ("lines_per_wave", ctypes.c_double),
+                ("max_lines_per_wave", ctypes.c_int64)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_free", ctypes.c_int32), ("n_mesh", ctypes.c_int32),
                 ("n_colors", ctypes.c_int32), ("n_tri", ctypes.c_int64), ("nnz_full", ctypes.c_int64),
@@ -77,6 +83,7 @@ _SIGS = {
     "lms_get_vertex_data": (ctypes.c_int, [_vp, _vp, _vp]),
     "lms_get_order": (ctypes.c_int, [_vp, _vp]),
     "lms_host_vertex_quality": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "lms_reuse_profile": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i32, _i32, ctypes.POINTER(ReuseStats)]),
 }
 
 
@@ -245,6 +252,18 @@ class Mesh:
         q = np.empty(self.n, dtype=np.float64)
         _check(load().lms_host_vertex_quality(self.handle, _np_ptr(x), _np_ptr(y), _np_ptr(q)))
         return q
+
+    def reuse_profile(self, fractions=(0.5, 0.75, 0.9, 1.0), line_bytes: int = 128,
+                      record_bytes: int = 16) -> dict:
+        """Locality of the current ordering (reuse-distance quantiles of one
+        sweep's access trace, cache-line spans per wavefront); host only."""
+        f = np.ascontiguousarray(fractions, dtype=np.float64)
+        q = np.zeros(f.size, dtype=np.int64)
+        st = ReuseStats()
+        _check(load().lms_reuse_profile(self.handle, _np_ptr(f), int(f.size), _np_ptr(q), int(line_bytes),
+                                        int(record_bytes), ctypes.byref(st)))
+        return dict(accesses=st.accesses, cold=st.cold, quantiles=[int(v) for v in q], mean=st.mean,
+                    max=st.max, lines_per_wave=st.lines_per_wave, max_lines_per_wave=st.max_lines_per_wave)
 
     # ---- device-side ------------------------------------------------------
     def permute(self, sx, sy, dx, dy, inverse: bool = False):

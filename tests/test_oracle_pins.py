@@ -511,3 +511,44 @@ def test_random_order_is_uniform_bijection():
     assert len(counts) == 6
     assert all(abs(c - 1000) < 150 for c in counts.values())
     assert oord.is_permutation(oord.random_order(1000, 7), 1000)
+
+
+# ---- reuse-distance profile (Section 2; Table 2's quantiles) --------------
+
+def test_reuse_distance_hand_example():
+    from oracle import reuse as ore
+    # a b c a b b: the second a sees {b, c}, the second b {c, a}, the third b nothing
+    for f in (ore.reuse_distances, ore.reuse_distances_brute):
+        d, cold = f([0, 1, 2, 0, 1, 1])
+        assert d.tolist() == [2, 2, 0] and cold == 3
+
+
+def test_reuse_distance_stack_matches_definition_on_random_traces():
+    from oracle import reuse as ore
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        tr = rng.integers(0, rng.integers(2, 30), size=rng.integers(1, 120))
+        a, ca = ore.reuse_distances(tr)
+        b, cb = ore.reuse_distances_brute(tr)
+        assert np.array_equal(a, b) and ca == cb
+
+
+def test_reuse_quantile_definition():
+    from oracle import reuse as ore
+    d = [4, 1, 3, 2]
+    assert [ore.quantile(d, x) for x in (0.0, 0.25, 0.5, 0.75, 0.9, 1.0)] == [1, 1, 2, 3, 4, 4]
+    assert ore.quantile([], 0.5) == 0
+
+
+def test_reuse_trace_and_line_spans_of_a_wheel():
+    from oracle import mesh as omesh
+    from oracle import reuse as ore
+    m = meshgen.wheel(8)                        # centre 0 (free), rim 1..8 (fixed)
+    top = omesh.topology(m.n, m.tri)
+    ident = np.arange(m.n)
+    assert ore.sweep_trace(top, ident).tolist() == [0, 1, 2, 3, 4, 5, 6, 7, 8]
+    d, cold = ore.reuse_distances(ore.sweep_trace(top, ident))
+    assert d.size == 0 and cold == 9
+    # rim records at bytes 16..128 of 16-byte records: lines 0 and 1 of 128 bytes
+    assert ore.wave_line_spans(top, ident).tolist() == [2]
+    assert ore.wave_line_spans(top, ident, line_bytes=64).tolist() == [3]
