@@ -497,12 +497,19 @@ def test_temporal_blocking_same_bits_as_single_sweeps(kind):
             for dt in (torch.float64, torch.float32):
                 os.environ["LMS_SWEEP_CONFIG"] = "36"       # one sweep per pass (halo-staged)
                 rx, ry, _, _ = run_library(m, kind, K, dtype=dt, M=M)
+                ran = 0
                 for cfg in range(44, 56):                    # width 8: depths 2 to 4
                     os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
-                    x, y, r, _ = run_library(m, kind, K, dtype=dt, M=M)
+                    try:
+                        x, y, r, _ = run_library(m, kind, K, dtype=dt, M=M)
+                    except lms.LmsError as e:                # plan gave up: halo rings too wide
+                        assert e.status == 1 and "cannot use" in str(e)
+                        continue
+                    ran += 1
                     assert M.sweep_config("f64" if dt == torch.float64 else "f32").startswith("tb/")
                     assert r["iters"] == K
                     assert np.array_equal(x, rx) and np.array_equal(y, ry), (cfg, K, str(dt))
+                assert ran >= 8, (kind, ran)
                 if dt == torch.float64:
                     assert np.max(np.abs(rx - ex)) <= TOL64 * extent(m.xy)
                     assert np.max(np.abs(ry - ey)) <= TOL64 * extent(m.xy)
