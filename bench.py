@@ -162,7 +162,7 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
     return out, (x, y)
 
 
-def cpu_baseline(m, sweeps, budget_s=3.0):
+def cpu_baseline(m, sweeps, budget_s=10.0):
     from oracle import mesh as omesh
     from oracle import smooth as osm
     top = omesh.topology(m.n, m.tri)
