@@ -281,6 +281,18 @@ def bench_ocean(torch, args):
         extras["stream_copy_gbs"] = stream_copy_gbs(torch)
         extras["host_seconds"] = dict(generate=t_gen, build_csr=t_csr,
                                       **{f"reorder_{k}": v for k, v in reorder_s.items()})
+        # the same reorders with the breadth-first search and the relabelling
+        # on the GPU (same result)
+        dev_s = {}
+        for kind in ORDER_NAMES:
+            want = M.reorder(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)
+            M.reorder_device(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)      # uploads the input arrays once
+            t0 = time.perf_counter()
+            got = M.reorder_device(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)
+            dev_s[kind] = time.perf_counter() - t0
+            assert np.array_equal(want, got)
+            log(f"reorder {kind:7s}: host {reorder_s.get(kind, float('nan')):.3f} s, device {dev_s[kind]:.3f} s")
+        extras["device_reorder_seconds"] = dev_s
         g = {k: results.get(f"{k}_f64", {}).get("vertex_updates_per_s") for k in ORDER_NAMES}
         if g.get("rdr") and g.get("ori") and g.get("bfs"):
             # the paper's gain metric (T_algo - T_RDR) / T_algo, here on the GPU
@@ -435,9 +447,14 @@ def bench_graded64m(torch, args):
     for kind in ("rdr", "random"):
         log(f"reordering ({kind}) ...")
         t0 = time.perf_counter()
-        M.reorder(kind, seed=RANDOM_SEED + 3, x0=m.x, y0=m.y)
+        want = M.reorder(kind, seed=RANDOM_SEED + 3, x0=m.x, y0=m.y)
         host[f"reorder_{kind}"] = time.perf_counter() - t0
-        log(f"reordered in {host[f'reorder_{kind}']:.1f}s")
+        log(f"reordered in {host[f'reorder_{kind}']:.1f}s on the host; again with the relabelling on the GPU ...")
+        t0 = time.perf_counter()
+        got = M.reorder_device(kind, seed=RANDOM_SEED + 3, x0=m.x, y0=m.y)
+        host[f"reorder_device_{kind}"] = time.perf_counter() - t0
+        assert np.array_equal(want, got)
+        log(f"reordered in {host[f'reorder_device_{kind}']:.1f}s (GPU relabelling, first call uploads the input)")
         x0 = torch.as_tensor(m.x, dtype=torch.float32, device="cuda")
         y0 = torch.as_tensor(m.y, dtype=torch.float32, device="cuda")
         x = torch.empty_like(x0)

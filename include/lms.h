@@ -145,6 +145,17 @@ lms_status lms_build_csr_batched(int32_t n_mesh, const int64_t *v_off, const int
 lms_status lms_reorder(lms_mesh_t m, lms_ordering kind, uint64_t seed,
                        const double *x0, const double *y0, int32_t *new2old);
 
+/* lms_reorder with the work on the GPU: LMS_BFS's breadth-first search
+ * (level-synchronous, one search from the smallest label of every component
+ * at once) and, for every kind, the relabelling of the handle's arrays (the
+ * permutation apply of Algorithm 2's V_new <- V: smoothing adjacency, padded
+ * copies, triangles, vertex-to-triangle lists).  RDR's walk and the random
+ * shuffle stay sequential on the host.  The resulting ordering and every
+ * array equal lms_reorder's, bit for bit.  Synchronous on `stream` (the
+ * current device); same arguments and errors as lms_reorder. */
+lms_status lms_reorder_device(lms_mesh_t m, lms_ordering kind, uint64_t seed,
+                              const double *x0, const double *y0, int32_t *new2old, void *stream);
+
 /* RDR (Algorithm 2) from given vertex qualities.
  *   q        host float64[n], quality per INPUT vertex
  *   new2old  host int32[n] out, or NULL

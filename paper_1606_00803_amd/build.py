@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "liblms.so")
 ARCH = os.environ.get("LMS_OFFLOAD_ARCH", "gfx950")
 
 HOST_SRC = ["lms_host.cpp", "lms_api.cpp"]
-HIP_SRC = ["lms_device.hip"]
+HIP_SRC = ["lms_device.hip", "lms_reorder.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "-Wall", "-Wextra", f"-I{INC}", f"-I{CSRC}"]
 

@@ -121,6 +121,18 @@ lms_status lms_reorder(lms_mesh_t m, lms_ordering kind, uint64_t seed, const dou
     });
 }
 
+lms_status lms_reorder_device(lms_mesh_t m, lms_ordering kind, uint64_t seed, const double *x0, const double *y0,
+                              int32_t *new2old, void *stream) {
+    return guarded([&] {
+        lms::Mesh &M = mesh_of(m);
+        std::vector<int32_t> given;
+        if (kind != LMS_BFS) given = make_order(M, kind, seed, x0, y0, nullptr);
+        std::vector<int32_t> p;
+        lms::dev_reorder(M, kind, given, stream, p);
+        if (new2old) std::memcpy(new2old, p.data(), sizeof(int32_t) * size_t(M.n));
+    });
+}
+
 lms_status lms_reorder_with_quality(lms_mesh_t m, const double *q, int32_t *new2old) {
     return guarded([&] {
         lms::Mesh &M = mesh_of(m);

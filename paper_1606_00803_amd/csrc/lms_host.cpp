@@ -341,33 +341,6 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
             for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j) ell[size_t(k) * size_t(ell_w) + size_t(j - row_ptr[k])] = col[j];
     }
 
-    std::vector<int32_t> color_ptr(size_t(M.n_colors) + 1, 0), color_list;
-    for (int32_t k = 0; k < n; ++k)
-        if (color[k] >= 0) color_ptr[color[k] + 1]++;
-    for (int32_t c = 0; c < M.n_colors; ++c) color_ptr[c + 1] += color_ptr[c];
-    color_list.resize(size_t(color_ptr[M.n_colors]));
-    {
-        std::vector<int32_t> fill(color_ptr.begin(), color_ptr.end() - 1);
-        for (int32_t k = 0; k < n; ++k)
-            if (color[k] >= 0) color_list[fill[color[k]]++] = k;
-    }
-
-    // colour-major padded copy for the multicolour sweep: one coalesced index
-    // load per entry for the vertices of one colour
-    std::vector<int32_t> color_ell;
-    if (ell_w > 0) {
-        resize_or_fail(color_ell, size_t(ell_w) * color_list.size());
-        std::fill(color_ell.begin(), color_ell.end(), -1);
-        for (int32_t c = 0; c < M.n_colors; ++c) {
-            const int64_t base = int64_t(ell_w) * color_ptr[c], cnt = color_ptr[c + 1] - color_ptr[c];
-            for (int64_t i = 0; i < cnt; ++i) {
-                const int32_t k = color_list[size_t(color_ptr[c] + i)];
-                for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j)
-                    color_ell[size_t(base + int64_t(j - row_ptr[k]) * cnt + i)] = col[j];
-            }
-        }
-    }
-
     // triangles: counting sort by smallest new id, stable in input index
     const int64_t T = M.T;
     std::vector<int64_t> bucket(size_t(n) + 1, 0);
@@ -426,6 +399,45 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
             vt[fill[ta[i]]++] = int32_t(i);
             vt[fill[tb[i]]++] = int32_t(i);
             vt[fill[tc[i]]++] = int32_t(i);
+        }
+    }
+
+    adopt_relabel(M, kind, std::move(new2old), std::move(old2new), std::move(row_ptr), std::move(col), ell_w,
+                  std::move(ell), std::move(fx), std::move(color), std::move(ta), std::move(tb), std::move(tc),
+                  std::move(tw), std::move(trec), std::move(tmesh), std::move(vt_ptr), std::move(vt));
+}
+
+void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std::vector<int32_t> old2new,
+                   std::vector<int32_t> row_ptr, std::vector<int32_t> col, int32_t ell_w, std::vector<int32_t> ell,
+                   std::vector<uint8_t> fx, std::vector<int32_t> color, std::vector<int32_t> ta,
+                   std::vector<int32_t> tb, std::vector<int32_t> tc, std::vector<double> tw,
+                   std::vector<int32_t> trec, std::vector<int32_t> tmesh, std::vector<int32_t> vt_ptr,
+                   std::vector<int32_t> vt) {
+    const int32_t n = M.n;
+    std::vector<int32_t> color_ptr(size_t(M.n_colors) + 1, 0), color_list;
+    for (int32_t k = 0; k < n; ++k)
+        if (color[k] >= 0) color_ptr[color[k] + 1]++;
+    for (int32_t c = 0; c < M.n_colors; ++c) color_ptr[c + 1] += color_ptr[c];
+    color_list.resize(size_t(color_ptr[M.n_colors]));
+    {
+        std::vector<int32_t> fill(color_ptr.begin(), color_ptr.end() - 1);
+        for (int32_t k = 0; k < n; ++k)
+            if (color[k] >= 0) color_list[fill[color[k]]++] = k;
+    }
+
+    // colour-major padded copy for the multicolour sweep: one coalesced index
+    // load per entry for the vertices of one colour
+    std::vector<int32_t> color_ell;
+    if (ell_w > 0) {
+        resize_or_fail(color_ell, size_t(ell_w) * color_list.size());
+        std::fill(color_ell.begin(), color_ell.end(), -1);
+        for (int32_t c = 0; c < M.n_colors; ++c) {
+            const int64_t base = int64_t(ell_w) * color_ptr[c], cnt = color_ptr[c + 1] - color_ptr[c];
+            for (int64_t i = 0; i < cnt; ++i) {
+                const int32_t k = color_list[size_t(color_ptr[c] + i)];
+                for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j)
+                    color_ell[size_t(base + int64_t(j - row_ptr[k]) * cnt + i)] = col[j];
+            }
         }
     }
 

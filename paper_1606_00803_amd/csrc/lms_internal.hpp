@@ -26,6 +26,13 @@ struct DeviceDeleter {
     void operator()(DeviceState *d) const { destroy_device_state(d); }
 };
 
+struct ReorderState;  // defined in lms_reorder.hip
+void destroy_reorder_state(ReorderState *r);
+
+struct ReorderDeleter {
+    void operator()(ReorderState *r) const { destroy_reorder_state(r); }
+};
+
 // Everything the host knows about a mesh.  Arrays suffixed 0 are in INPUT
 // labels and never change after the build; the rest follow the current
 // ordering and are rebuilt by relabel().
@@ -130,6 +137,7 @@ struct Mesh {
     uint64_t version = 0;
 
     std::unique_ptr<DeviceState, DeviceDeleter> dev;
+    std::unique_ptr<ReorderState, ReorderDeleter> rdev;  // input arrays for the device reorder
 };
 
 // ---- host logic (lms_host.cpp) ----
@@ -140,6 +148,13 @@ std::vector<int32_t> order_bfs(const Mesh &M);
 std::vector<int32_t> order_rdr(const Mesh &M, const double *q);
 std::vector<int32_t> order_random(const Mesh &M, uint64_t seed);
 void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old);
+// Install the arrays of a new labelling (colour lists built here).
+void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std::vector<int32_t> old2new,
+                   std::vector<int32_t> row_ptr, std::vector<int32_t> col, int32_t ell_w, std::vector<int32_t> ell,
+                   std::vector<uint8_t> fx, std::vector<int32_t> color, std::vector<int32_t> ta,
+                   std::vector<int32_t> tb, std::vector<int32_t> tc, std::vector<double> tw,
+                   std::vector<int32_t> trec, std::vector<int32_t> tmesh, std::vector<int32_t> vt_ptr,
+                   std::vector<int32_t> vt);
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap);
 void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
@@ -154,6 +169,9 @@ void dev_sweep(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,
 void dev_smooth(Mesh &M, void *x, void *y, void *tx, void *ty, lms_precision p,
                 lms_scheme s, const lms_smooth_opts &o, void *stream, lms_smooth_result &r);
 std::string dev_sweep_config(Mesh &M, lms_precision p);
+// ---- device reorder (lms_reorder.hip) ----
+void dev_reorder(Mesh &M, lms_ordering kind, const std::vector<int32_t> &given, void *stream,
+                 std::vector<int32_t> &new2old_out);
 void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global,
                  double *q_vertex, double *q_mesh, void *stream);
 

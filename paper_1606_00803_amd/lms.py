@@ -83,6 +83,7 @@ _SIGS = {
     "lms_get_vertex_data": (ctypes.c_int, [_vp, _vp, _vp]),
     "lms_get_order": (ctypes.c_int, [_vp, _vp]),
     "lms_host_vertex_quality": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "lms_reorder_device": (ctypes.c_int, [_vp, _i32, _u64, _vp, _vp, _vp, _vp]),
     "lms_reuse_profile": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i32, _i32, ctypes.POINTER(ReuseStats)]),
 }
 
@@ -217,6 +218,23 @@ class Mesh:
             xp, yp = _np_ptr(x0), _np_ptr(y0)
         _check(load().lms_reorder(self.handle, kind, ctypes.c_uint64(seed & (2**64 - 1)), xp, yp,
                                   _np_ptr(out)))
+        return out
+
+    def reorder_device(self, kind, seed: int = 0, x0=None, y0=None) -> np.ndarray:
+        """reorder() with the breadth-first search and the relabelling on the
+        GPU (same result, bit for bit)."""
+        kind = ORDERINGS[kind] if isinstance(kind, str) else int(kind)
+        n = self.n
+        out = np.empty(n, dtype=np.int32)
+        xp = yp = None
+        if x0 is not None:
+            x0 = np.ascontiguousarray(x0, dtype=np.float64)
+            y0 = np.ascontiguousarray(y0, dtype=np.float64)
+            if x0.size != n or y0.size != n:
+                raise ValueError("x0, y0 must have n elements")
+            xp, yp = _np_ptr(x0), _np_ptr(y0)
+        _check(load().lms_reorder_device(self.handle, kind, ctypes.c_uint64(seed & (2**64 - 1)), xp, yp,
+                                         _np_ptr(out), _stream()))
         return out
 
     def reorder_with_quality(self, q) -> np.ndarray:

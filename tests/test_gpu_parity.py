@@ -604,3 +604,65 @@ def test_fused_quality_stopping_rule_matches_separate_passes(prec, cfg):
     finally:
         os.environ.pop("LMS_FUSED_QUALITY", None)
         os.environ.pop("LMS_SWEEP_CONFIG", None)
+
+
+def _reorder_cases():
+    grid = meshgen.jittered_grid(97, 83, seed=51, land_fraction=0.3)
+    pair = meshgen.concat([meshgen.jittered_grid(31, 29, seed=52), meshgen.jittered_grid(23, 37, seed=53)])[0]
+    batch = meshgen.batch(count=40, seed=54, n_min=60, n_max=3000)
+    wheel = meshgen.wheel(3000, seed=5)
+    return [("grid", grid, None), ("pair", pair, None), ("batch", None, batch), ("wheel", wheel, None)]
+
+
+@pytest.mark.parametrize("kind", ["ori", "bfs", "rdr", "random"])
+def test_device_reorder_equals_host_reorder(kind):
+    # the GPU's breadth-first search and relabelling give what the host path
+    # gives, bit for bit: order, adjacency, vertex data, and (through the
+    # triangle order and the vertex -> triangle lists) the quality sums
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    for name, m, batch in _reorder_cases():
+        if batch is not None:
+            u, v_off, t_off = meshgen.concat(batch)
+            local = np.concatenate([b.tri for b in batch])
+            Mh = lms.Mesh.build_csr_batched(v_off, t_off, local)
+            Md = lms.Mesh.build_csr_batched(v_off, t_off, local)
+            m = u
+        else:
+            Mh = lms.Mesh.build_csr(m.n, m.tri)
+            Md = lms.Mesh.build_csr(m.n, m.tri)
+        ph = Mh.reorder(kind, seed=9, x0=m.x, y0=m.y)
+        pd = Md.reorder_device(kind, seed=9, x0=m.x, y0=m.y)
+        assert np.array_equal(ph, pd), (name, kind)
+        assert np.array_equal(Mh.order(), Md.order())
+        for a, b in zip(Mh.csr(), Md.csr()):
+            assert np.array_equal(a, b), (name, kind)
+        for a, b in zip(Mh.vertex_data(), Md.vertex_data()):
+            assert np.array_equal(a, b), (name, kind)
+        if kind == "bfs":
+            assert np.array_equal(pd, oord.bfs(oracle_topology(m))), name
+        x0 = to_dev(m.x, torch.float64)
+        y0 = to_dev(m.y, torch.float64)
+        xh, yh, xd, yd = (torch.empty_like(x0) for _ in range(4))
+        Mh.permute(x0, y0, xh, yh)
+        Md.permute(x0, y0, xd, yd)
+        qvh = torch.empty_like(x0)
+        qvd = torch.empty_like(x0)
+        assert Mh.quality(xh, yh, qvh) == Md.quality(xd, yd, qvd), (name, kind)
+        assert torch.equal(qvh, qvd)
+        rh = Mh.smooth(xh, yh, max_iters=200, check_quality=True)
+        rd = Md.smooth(xd, yd, max_iters=200, check_quality=True)
+        torch.cuda.synchronize()
+        # each handle tunes its own variants, so Q may be summed in another order
+        assert (rh["iters"], rh["stopped_by"]) == (rd["iters"], rd["stopped_by"]), (name, kind)
+        for key in ("q0", "q_final", "last_dq"):
+            assert abs(rh[key] - rd[key]) <= 1e-12, (name, kind, key)
+        assert torch.equal(xh, xd) and torch.equal(yh, yd), (name, kind)
+
+
+def test_device_bfs_matches_the_oracle_on_several_components():
+    from paper_1606_00803_amd import lms
+    parts = [meshgen.jittered_grid(40 + 7 * i, 33, seed=60 + i, land_fraction=0.25) for i in range(5)]
+    m = meshgen.concat(parts)[0]
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    assert np.array_equal(M.reorder_device("bfs"), oord.bfs(oracle_topology(m)))
