@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <limits>
 #include <string>
 #include <vector>
@@ -1263,7 +1264,7 @@ struct DeviceState {
         int32_t *halo_ptr = nullptr, *halo = nullptr;
         uint16_t *lidx = nullptr;
     };
-    std::vector<HaloDev> halos;  // uploaded tile plans of the current version
+    std::deque<HaloDev> halos;   // uploaded tile plans of the current version (stable references)
     struct TBDev {
         int32_t ts = 0, k = 0, u_cap = 0, l_cap = 0, tiles = 0, l_max = 0, u_max = 0;
         bool fits = false;
@@ -1279,7 +1280,7 @@ struct DeviceState {
         double *qc_w = nullptr;
         int64_t n_qc = 0;
     };
-    std::vector<TBDev> tbs;      // uploaded temporal-blocking plans of the current version
+    std::deque<TBDev> tbs;       // uploaded temporal-blocking plans of the current version
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
     double *tw = nullptr;
     int32_t *trec = nullptr;
@@ -1338,6 +1339,17 @@ void end_call(DeviceState &d, hipStream_t s) {
     HIP_CHECK(hipEventRecord(d.last_done, s));
     d.last_stream = s;
     d.last_valid = true;
+}
+
+// Free one array of the current version's set (it must be in d.arrays).
+void free_array(DeviceState &d, const void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < d.arrays.size(); ++i)
+        if (d.arrays[i] == p) {
+            (void)hipFree(d.arrays[i]);
+            d.arrays.erase(d.arrays.begin() + std::ptrdiff_t(i));
+            return;
+        }
 }
 
 void free_arrays(DeviceState *d) {
@@ -1914,6 +1926,60 @@ vec2_t<T> *ensure_packed(DeviceState &d, int which, int32_t n) {
     return static_cast<vec2_t<T> *>(d.pk[pi][which]);
 }
 
+// Meshes from this many rows on drop, after each tuning, the tile plans that
+// no tuned precision's chosen variants use (host and device): there each plan
+// costs ~20-40 bytes per row, and the tuner builds a dozen.
+constexpr int32_t kDropPlansFrom = 1 << 22;
+
+void drop_unused_plans(DeviceState &d, Mesh &M) {
+    std::vector<int> keep;
+    for (int pi = 0; pi < 2; ++pi)
+        for (int c : {d.sweep_cfg[pi], d.smooth_cfg[pi], d.tb_cfg[pi], d.tb_best[pi]})
+            if (c >= 0) keep.push_back(c);
+    auto keep_ts = [&](int32_t ts) {
+        for (int c : keep)
+            if (!is_tb_config(c) && sweep_config_tile(c) == ts) return true;
+        return false;
+    };
+    auto keep_tb = [&](int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap) {
+        for (int c : keep)
+            if (is_tb_config(c)) {
+                const TBShape t = tb_shape(c);
+                if (t.ts == ts && t.k == k && t.bs * t.r == u_cap && t.lcap == l_cap) return true;
+            }
+        return false;
+    };
+    wait_idle(d);
+    for (auto it = d.halos.begin(); it != d.halos.end();) {
+        if (keep_ts(it->ts)) {
+            ++it;
+            continue;
+        }
+        free_array(d, it->halo_ptr);
+        free_array(d, it->halo);
+        free_array(d, it->lidx);
+        it = d.halos.erase(it);
+    }
+    for (auto it = d.tbs.begin(); it != d.tbs.end();) {
+        if (keep_tb(it->ts, it->k, it->u_cap, it->l_cap)) {
+            ++it;
+            continue;
+        }
+        for (const void *p : {static_cast<const void *>(it->tile_ptr), static_cast<const void *>(it->ring),
+                              static_cast<const void *>(it->halo), static_cast<const void *>(it->halo_ptr),
+                              static_cast<const void *>(it->lidx_ptr), static_cast<const void *>(it->lidx),
+                              static_cast<const void *>(it->qtri_ptr), static_cast<const void *>(it->qtri),
+                              static_cast<const void *>(it->qpart), static_cast<const void *>(it->qc_ids),
+                              static_cast<const void *>(it->qc_w)})
+            free_array(d, p);
+        it = d.tbs.erase(it);
+    }
+    for (auto it = M.halo_plans.begin(); it != M.halo_plans.end();)
+        it = keep_ts(it->ts) ? std::next(it) : M.halo_plans.erase(it);
+    for (auto it = M.tb_plans.begin(); it != M.tb_plans.end();)
+        it = keep_tb(it->ts, it->k, it->u_cap, it->l_cap) ? std::next(it) : M.tb_plans.erase(it);
+}
+
 // Autotuner: time every sweep variant on this mesh (src -> dst, which leaves
 // dst holding one sweep of src) and keep the fastest for the handle's current
 // ordering and this precision.  LMS_SWEEP_CONFIG=<id> forces a variant;
@@ -2001,6 +2067,7 @@ void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
     d.smooth_cfg[pi] = best_all;
     d.tb_cfg[pi] = best_tb >= 0 && best_tb_ms < best_all_ms ? best_tb : -1;
     d.tb_best[pi] = best_tb;
+    if (M.n >= kDropPlansFrom) drop_unused_plans(d, M);
     if (env_flag("LMS_VERBOSE", false)) {
         std::fprintf(stderr,
                      "[lms] sweep autotune (%s, n=%d): %s, %.2f us (separate arrays: %s, %.2f us; "

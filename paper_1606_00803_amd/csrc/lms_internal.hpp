@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <deque>
 #include <vector>
 
 #include "lms.h"
@@ -91,7 +92,7 @@ struct Mesh {
         std::vector<uint16_t> lidx;     // tiles * ell_w * ts
         uint64_t version = ~uint64_t(0);
     };
-    std::vector<HaloPlan> halo_plans;
+    std::deque<HaloPlan> halo_plans;  // deque: references stay valid as plans are added
 
     // Tile plan of the temporally blocked sweep (k Jacobi sweeps per pass).
     // Tiles are ranges of consecutive rows: nominally ts rows, halved until
@@ -130,7 +131,7 @@ struct Mesh {
         std::vector<double> qc_w;       // its weight 1/|T(a)| + 1/|T(b)| + 1/|T(c)|
         uint64_t version = ~uint64_t(0);
     };
-    std::vector<TBPlan> tb_plans;
+    std::deque<TBPlan> tb_plans;
 
     // generation counter: bumped whenever the current labelling changes so
     // that device copies and captured graphs are refreshed
