@@ -5,6 +5,7 @@
 // computed with exactly the IEEE operations written here, so any other code
 // performing the same operations in the same order gets the same bits.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -29,6 +30,34 @@ void resize_or_fail(std::vector<T> &v, size_t n) {
     } catch (const std::bad_alloc &) {
         fail(LMS_ERR_ALLOC, "host allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
     }
+}
+
+
+int host_threads(int64_t work_items) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t t = std::min<int64_t>(std::min<int64_t>(hw == 0 ? 1 : hw, 16), std::max<int64_t>(1, work_items / 64));
+    return int(std::max<int64_t>(1, t));
+}
+
+// Runs f(worker, first, last) over [0, items) split into contiguous runs,
+// one thread each; rethrows the first exception.
+template <class F>
+void parallel_runs(int64_t items, int workers, F f) {
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(static_cast<size_t>(workers));
+    for (int w = 0; w < workers; ++w) {
+        const int64_t first = items * w / workers, last = items * (w + 1) / workers;
+        th.emplace_back([&, w, first, last]() {
+            try {
+                f(w, first, last);
+            } catch (...) {
+                err[size_t(w)] = std::current_exception();
+            }
+        });
+    }
+    for (auto &t : th) t.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 }  // namespace
@@ -161,27 +190,31 @@ void build_mesh(Mesh &M, int32_t n, int64_t T, const int32_t *tri, const uint8_t
 // triangles, summed in ascending triangle index.
 void vertex_quality_host(const Mesh &M, const double *x, const double *y, double *q) {
     std::vector<double> qt(static_cast<size_t>(M.T));
-    for (int64_t t = 0; t < M.T; ++t) {
-        const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
-        double dx, dy;
-        dx = x[b] - x[a];
-        dy = y[b] - y[a];
-        const double e0 = dx * dx + dy * dy;
-        dx = x[c] - x[b];
-        dy = y[c] - y[b];
-        const double e1 = dx * dx + dy * dy;
-        dx = x[a] - x[c];
-        dy = y[a] - y[c];
-        const double e2 = dx * dx + dy * dy;
-        const double mn = std::min(std::min(e0, e1), e2);
-        const double mx = std::max(std::max(e0, e1), e2);
-        qt[t] = mx > 0.0 ? std::sqrt(mn) / std::sqrt(mx) : 0.0;
-    }
-    for (int32_t v = 0; v < M.n; ++v) {
-        double s = 0.0;
-        for (int64_t i = M.vt_ptr0[v]; i < M.vt_ptr0[v + 1]; ++i) s += qt[M.vt0[i]];
-        q[v] = s / double(M.tcount0[v]);
-    }
+    parallel_runs(M.T, host_threads(M.T / 1024), [&](int, int64_t first, int64_t last) {
+        for (int64_t t = first; t < last; ++t) {
+            const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
+            double dx, dy;
+            dx = x[b] - x[a];
+            dy = y[b] - y[a];
+            const double e0 = dx * dx + dy * dy;
+            dx = x[c] - x[b];
+            dy = y[c] - y[b];
+            const double e1 = dx * dx + dy * dy;
+            dx = x[a] - x[c];
+            dy = y[a] - y[c];
+            const double e2 = dx * dx + dy * dy;
+            const double mn = std::min(std::min(e0, e1), e2);
+            const double mx = std::max(std::max(e0, e1), e2);
+            qt[size_t(t)] = mx > 0.0 ? std::sqrt(mn) / std::sqrt(mx) : 0.0;
+        }
+    });
+    parallel_runs(M.n, host_threads(M.n / 1024), [&](int, int64_t first, int64_t last) {
+        for (int64_t v = first; v < last; ++v) {
+            double s = 0.0;
+            for (int64_t i = M.vt_ptr0[size_t(v)]; i < M.vt_ptr0[size_t(v) + 1]; ++i) s += qt[size_t(M.vt0[size_t(i)])];
+            q[v] = s / double(M.tcount0[size_t(v)]);
+        }
+    });
 }
 
 // Breadth-first search from label 0, neighbours in ascending label, restart
@@ -221,23 +254,67 @@ std::vector<int32_t> order_bfs(const Mesh &M) {
 // loop then continues over the fixed vertices, which places the ones the
 // interior loop never reaches (Theorem 1 misses a fixed vertex whose
 // neighbours are all fixed and never walked onto).
+namespace {
+
+// A vertex and its quality; RDR's order is ascending (q, label).
+struct QV {
+    double q;
+    int32_t v;
+};
+inline bool qv_less(const QV &a, const QV &b) { return a.q < b.q || (a.q == b.q && a.v < b.v); }
+
+// Sort by (q, label): sorted runs on several threads, then rounds of pairwise
+// merges.  Keys are distinct (labels are), so the result is the sorted order.
+void parallel_sort_qv(std::vector<QV> &a) {
+    const int64_t n = int64_t(a.size());
+    const int P = host_threads(n / 4096);
+    if (P <= 1) {
+        std::sort(a.begin(), a.end(), qv_less);
+        return;
+    }
+    std::vector<int64_t> bound(size_t(P) + 1);
+    for (int i = 0; i <= P; ++i) bound[size_t(i)] = n * i / P;
+    parallel_runs(P, P, [&](int, int64_t first, int64_t last) {
+        for (int64_t r = first; r < last; ++r)
+            std::sort(a.begin() + bound[size_t(r)], a.begin() + bound[size_t(r) + 1], qv_less);
+    });
+    std::vector<QV> tmp(a.size());
+    for (int64_t width = 1; width < P; width *= 2) {
+        std::vector<std::array<int64_t, 3>> jobs;
+        for (int64_t i = 0; i < P; i += 2 * width)
+            jobs.push_back({bound[size_t(i)], bound[size_t(std::min<int64_t>(i + width, P))],
+                            bound[size_t(std::min<int64_t>(i + 2 * width, P))]});
+        parallel_runs(int64_t(jobs.size()), int(jobs.size()), [&](int, int64_t first, int64_t last) {
+            for (int64_t j = first; j < last; ++j) {
+                const auto &[lo, mid, hi] = jobs[size_t(j)];
+                std::merge(a.begin() + lo, a.begin() + mid, a.begin() + mid, a.begin() + hi, tmp.begin() + lo, qv_less);
+            }
+        });
+        a.swap(tmp);
+    }
+}
+
+}  // namespace
+
 std::vector<int32_t> order_rdr(const Mesh &M, const double *q) {
-    auto less = [q](int32_t a, int32_t b) { return q[a] < q[b] || (q[a] == q[b] && a < b); };
     std::vector<int32_t> out;
     out.reserve(size_t(M.n));
     std::vector<uint8_t> processed(size_t(M.n), 0), placed(size_t(M.n), 0);
-    std::vector<int32_t> cur;
+    std::vector<QV> cur;
     auto place = [&](int32_t v) {
         if (!placed[v]) {
             placed[v] = 1;
             out.push_back(v);
         }
     };
+    // l of Algorithm 2: the unprocessed neighbours of w by increasing (q, label)
     auto unprocessed_neighbours = [&](int32_t w) {
         cur.clear();
-        for (int64_t j = M.adj_ptr0[w]; j < M.adj_ptr0[w + 1]; ++j)
-            if (!processed[M.adj0[j]]) cur.push_back(M.adj0[j]);
-        std::sort(cur.begin(), cur.end(), less);
+        for (int64_t j = M.adj_ptr0[w]; j < M.adj_ptr0[w + 1]; ++j) {
+            const int32_t u = M.adj0[j];
+            if (!processed[u]) cur.push_back(QV{q[u], u});
+        }
+        std::sort(cur.begin(), cur.end(), qv_less);
     };
     auto start_from = [&](int32_t i) {
         if (processed[i]) return;
@@ -245,21 +322,21 @@ std::vector<int32_t> order_rdr(const Mesh &M, const double *q) {
         processed[i] = 1;
         unprocessed_neighbours(i);
         while (!cur.empty()) {
-            for (int32_t u : cur) place(u);
-            const int32_t w = cur[0];
+            for (const QV &u : cur) place(u.v);
+            const int32_t w = cur[0].v;
             processed[w] = 1;
             unprocessed_neighbours(w);
         }
     };
-    std::vector<int32_t> seeds;
+    std::vector<QV> seeds;
     for (int32_t mi = 0; mi < M.n_mesh; ++mi) {
         const int32_t vb = int32_t(M.v_off[mi]), ve = int32_t(M.v_off[mi + 1]);
         for (int pass = 0; pass < 2; ++pass) {
             seeds.clear();
             for (int32_t v = vb; v < ve; ++v)
-                if ((M.fixed0[v] != 0) == (pass == 1)) seeds.push_back(v);
-            std::sort(seeds.begin(), seeds.end(), less);
-            for (int32_t i : seeds) start_from(i);
+                if ((M.fixed0[v] != 0) == (pass == 1)) seeds.push_back(QV{q[v], v});
+            parallel_sort_qv(seeds);
+            for (const QV &i : seeds) start_from(i.v);
         }
     }
     return out;
@@ -598,33 +675,6 @@ struct TBPart {
     std::vector<uint16_t> lidx;
     int32_t l_max = 0, u_max = 0;
 };
-
-int host_threads(int64_t work_items) {
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int64_t t = std::min<int64_t>(std::min<int64_t>(hw == 0 ? 1 : hw, 16), std::max<int64_t>(1, work_items / 64));
-    return int(std::max<int64_t>(1, t));
-}
-
-// Runs f(worker, first, last) over [0, items) split into contiguous runs,
-// one thread each; rethrows the first exception.
-template <class F>
-void parallel_runs(int64_t items, int workers, F f) {
-    std::vector<std::thread> th;
-    std::vector<std::exception_ptr> err(static_cast<size_t>(workers));
-    for (int w = 0; w < workers; ++w) {
-        const int64_t first = items * w / workers, last = items * (w + 1) / workers;
-        th.emplace_back([&, w, first, last]() {
-            try {
-                f(w, first, last);
-            } catch (...) {
-                err[size_t(w)] = std::current_exception();
-            }
-        });
-    }
-    for (auto &t : th) t.join();
-    for (auto &e : err)
-        if (e) std::rethrow_exception(e);
-}
 
 }  // namespace
 
