@@ -1072,6 +1072,34 @@ __global__ __launch_bounds__(256) void k_stop(const double *__restrict__ partial
 // s+j the final state is j sweeps past the pass's source copy: record both;
 // else advance `swept` past the pass.  Each thread sums a fixed set of tiles
 // (four independent loads in flight), so the order is the same every run.
+// First level of the fused stopping rule's sum when there are many tiles:
+// block b sums its fixed slice of the tiles' partials for each state the
+// pass evaluated (the same shape every run, so the same order).
+__global__ __launch_bounds__(256) void k_sum_tiles(const double *__restrict__ qpart, int32_t tiles, int32_t kp,
+                                                   const StopState *__restrict__ st, int32_t max_iters,
+                                                   double *__restrict__ out) {
+    __shared__ double s_red[4];
+    if (st->done) return;
+    const int32_t k = min(kp, max_iters - st->swept);
+    const int32_t nq = k > 0 ? k : 1;
+    const int64_t P = gridDim.x, b = blockIdx.x;
+    const int64_t lo = b * tiles / P, hi = (b + 1) * tiles / P;
+    for (int32_t j = 0; j < nq; ++j) {
+        const double *p = qpart + int64_t(j) * tiles;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * 256) {
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = i0 + q * 256 < hi ? p[i0 + q * 256] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += v[q];
+        }
+        const double sum = block_sum<256>((acc[0] + acc[1]) + (acc[2] + acc[3]), s_red);
+        if (threadIdx.x == 0) out[int64_t(j) * P + b] = sum;
+        __syncthreads();
+    }
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_stop_tb(const double *__restrict__ qpart, int32_t tiles, int32_t kp,
                                                 StopState *st, StopArgs a) {
@@ -1276,6 +1304,8 @@ struct DeviceState {
         int64_t *qtri_ptr = nullptr;
         uint32_t *qtri = nullptr;
         double *qpart = nullptr;  // k x tiles partial sums
+        double *qpart2 = nullptr; // k x nsum first-level sums (many tiles), else unused
+        int32_t nsum = 0;
         int32_t *qc_ids = nullptr;
         double *qc_w = nullptr;
         int64_t n_qc = 0;
@@ -1294,7 +1324,8 @@ struct DeviceState {
     double *qout = nullptr;
     double *qmesh = nullptr;
     StopState *st = nullptr;
-    StopState *h_st = nullptr;  // pinned host mirror
+    StopState *h_st = nullptr;  // two pinned host mirrors (the check of chunk i while chunk i+1 runs)
+    hipEvent_t st_ev[2] = {nullptr, nullptr};
     void *tmp[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [precision][x|y]
     size_t tmp_n[2] = {0, 0};
     hipStream_t cap = nullptr;
@@ -1387,7 +1418,8 @@ DeviceState &ensure_device(Mesh &M) {
         d->nparts = kQualMaxBlocks;
         HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d->qout), sizeof(double)));
         HIP_CHECK(hipMalloc(reinterpret_cast<void **>(&d->st), sizeof(StopState)));
-        HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&d->h_st), sizeof(StopState), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&d->h_st), 2 * sizeof(StopState), hipHostMallocDefault));
+        for (auto &e : d->st_ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&d->last_done, hipEventDisableTiming));
     }
     DeviceState *d = M.dev.get();
@@ -1766,6 +1798,9 @@ bool ensure_tbq(DeviceState &d, Mesh &M, const TBShape &t) {
     h->qc_w = upload(&d, P->qc_w);
     h->n_qc = int64_t(P->qc_w.size());
     h->qpart = upload(&d, std::vector<double>(size_t(t.k) * size_t(std::max(h->tiles, 1)), 0.0));
+    // more than 8192 tiles: a first level of ~2048 tiles per block
+    h->nsum = h->tiles > 8192 ? std::min(1024, (h->tiles + 2047) / 2048) : 0;
+    h->qpart2 = upload(&d, std::vector<double>(size_t(t.k) * size_t(std::max(h->nsum, 1)), 0.0));
     return true;
 }
 
@@ -2252,6 +2287,37 @@ void launch_small_meshes(DeviceState &d, const Mesh &M, vec2_t<T> *A, vec2_t<T> 
     launch_check();
 }
 
+// Runs the stopping rule's chunks and returns the final device state.  One
+// chunk stays queued ahead of the host's check: chunk i+1 is issued before
+// the state after chunk i is read back.  The stop flag never goes down and
+// all work after it returns at once, so a chunk issued past the stop changes
+// nothing.  `max_chunks` bounds the run (each chunk advances or ends it).
+template <class F>
+StopState run_stop_chunks(DeviceState &d, hipStream_t s, int64_t max_chunks, F issue_chunk) {
+    issue_chunk();
+    for (int64_t i = 0;; ++i) {
+        StopState *slot = d.h_st + (i & 1);
+        HIP_CHECK(hipMemcpyAsync(slot, d.st, sizeof(StopState), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipEventRecord(d.st_ev[i & 1], s));
+        if (i <= max_chunks) issue_chunk();
+        HIP_CHECK(hipEventSynchronize(d.st_ev[i & 1]));
+        if (slot->done) return *slot;
+        if (i > max_chunks) fail(LMS_ERR_STATE, "the stopping rule made no progress");
+    }
+}
+
+// The stopping rule after one quality-fused pass: the tiles' sums, in one or
+// two fixed-shape levels, then the rule.
+void launch_stop_tb(const DeviceState &d, const DeviceState::TBDev &h, int32_t kp, int32_t max_iters,
+                    const StopArgs &sa, hipStream_t s) {
+    if (h.nsum > 0) {
+        k_sum_tiles<<<h.nsum, 256, 0, s>>>(h.qpart, h.tiles, kp, d.st, max_iters, h.qpart2);
+        k_stop_tb<1024><<<1, 1024, 0, s>>>(h.qpart2, h.nsum, kp, d.st, sa);
+    } else {
+        k_stop_tb<1024><<<1, 1024, 0, s>>>(h.qpart, h.tiles, kp, d.st, sa);
+    }
+}
+
 // Passes per captured chunk of the quality-fused stopping rule (even, so that
 // every chunk starts from copy A).
 constexpr int kFusedChunk = 8;
@@ -2341,11 +2407,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                                 dbl_key(o.goal) + "|" + std::to_string(o.max_iters);
         // every chunk advances at least kFusedChunk*depth sweeps or ends the run
         const int64_t max_chunks = (int64_t(o.max_iters) + 1) / (int64_t(kFusedChunk) * t.k) + 2;
-        for (int64_t chunk = 0;; ++chunk) {
-            HIP_CHECK(hipMemcpyAsync(d.h_st, d.st, sizeof(StopState), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
-            if (d.h_st->done) break;
-            if (chunk > max_chunks) fail(LMS_ERR_STATE, "the fused stopping rule made no progress");
+        const StopState hs = run_stop_chunks(d, s, max_chunks, [&]() {
             run_maybe_graph(d, key, s, [&](hipStream_t cs) {
                 for (int q = 0; q < kFusedChunk; ++q) {
                     StopArgs sa{};
@@ -2357,11 +2419,10 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                     sa.max_iters = o.max_iters;
                     sa.src_index = q % 2;
                     launch_tb_cfg<T>(fq, d, M, q % 2 == 0 ? A : B, q % 2 == 0 ? B : A, 0, cs, true, o.max_iters);
-                    k_stop_tb<1024><<<1, 1024, 0, cs>>>(h->qpart, h->tiles, t.k, d.st, sa);
+                    launch_stop_tb(d, *h, t.k, o.max_iters, sa, cs);
                 }
             });
-        }
-        const StopState hs = *d.h_st;
+        });
         vec2_t<T> *fsrc = hs.src == 0 ? A : B, *fother = hs.src == 0 ? B : A;
         if (hs.redo > 0) launch_tb_cfg<T>(fq, d, M, fsrc, fother, hs.redo, s);
         in_b = (hs.redo > 0 ? fother : fsrc) == B;
@@ -2377,10 +2438,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         launch_check();
         const std::string key = "stop|" + base + "|" + dbl_key(o.tol) + "|" + dbl_key(o.goal) + "|" +
                                 std::to_string(o.max_iters);
-        for (;;) {
-            HIP_CHECK(hipMemcpyAsync(d.h_st, d.st, sizeof(StopState), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
-            if (d.h_st->done) break;
+        const StopState h = run_stop_chunks(d, s, int64_t(o.max_iters) / kChunk + 2, [&]() {
             run_maybe_graph(d, key, s, [&](hipStream_t cs) {
                 for (int k = 0; k < kChunk; ++k) {
                     vec2_t<T> *src = k % 2 == 0 ? A : B, *dst = k % 2 == 0 ? B : A;
@@ -2394,8 +2452,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                     launch_stop(d, M, 0, o, cs);
                 }
             });
-        }
-        const StopState h = *d.h_st;
+        });
         iters = h.iters;
         r.stopped_by = h.stopped_by;
         r.q0 = h.q0;
@@ -2470,10 +2527,7 @@ void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precisi
     launch_check();
     const std::string key = "stop|" + base + "|" + std::to_string(int(sch)) + "|" + dbl_key(o.tol) + "|" + dbl_key(o.goal) +
                             "|" + std::to_string(o.max_iters);
-    for (;;) {
-        HIP_CHECK(hipMemcpyAsync(d.h_st, d.st, sizeof(StopState), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        if (d.h_st->done) break;
+    const StopState h = run_stop_chunks(d, s, int64_t(o.max_iters) / kChunk + 2, [&]() {
         run_maybe_graph(d, key, s, [&](hipStream_t cs) {
             for (int k = 0; k < kChunk; ++k) {
                 const bool fwd = (k % 2 == 0);
@@ -2490,8 +2544,7 @@ void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precisi
                 launch_stop(d, M, 0, o, cs);
             }
         });
-    }
-    const StopState h = *d.h_st;
+    });
     if (jacobi && (h.iters % 2 == 1)) {
         HIP_CHECK(hipMemcpyAsync(x, tx, bytes, hipMemcpyDeviceToDevice, s));
         HIP_CHECK(hipMemcpyAsync(y, ty, bytes, hipMemcpyDeviceToDevice, s));
@@ -2524,6 +2577,8 @@ void destroy_device_state(DeviceState *d) {
     if (d->qout) (void)hipFree(d->qout);
     if (d->st) (void)hipFree(d->st);
     if (d->h_st) (void)hipHostFree(d->h_st);
+    for (auto e : d->st_ev)
+        if (e) (void)hipEventDestroy(e);
     if (d->cap) (void)hipStreamDestroy(d->cap);
     if (d->last_done) (void)hipEventDestroy(d->last_done);
     if (cur >= 0) (void)hipSetDevice(cur);
