@@ -666,3 +666,28 @@ def test_device_bfs_matches_the_oracle_on_several_components():
     m = meshgen.concat(parts)[0]
     M = lms.Mesh.build_csr(m.n, m.tri)
     assert np.array_equal(M.reorder_device("bfs"), oord.bfs(oracle_topology(m)))
+
+
+def test_batched_stopping_rule_matches_the_oracle_on_the_union():
+    # a batched handle's stopping rule uses Q over all its vertices: the
+    # union mesh's Q (fused and separate quality paths alike)
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    ms = meshgen.batch(count=20, seed=71, n_min=200, n_max=6000)
+    u, v_off, t_off = meshgen.concat(ms)
+    ref = osm.smooth(oracle_topology(u), u.x, u.y, max_iters=2000)
+    assert ref.stopped_by == "tol"
+    local = np.concatenate([m.tri for m in ms])
+    outs = {}
+    for fused in ("1", "0"):
+        os.environ["LMS_FUSED_QUALITY"] = fused
+        try:
+            B = lms.Mesh.build_csr_batched(v_off, t_off, local)
+            x, y, r, _ = run_library(u, "rdr", 2000, M=B, check_quality=True)
+        finally:
+            os.environ.pop("LMS_FUSED_QUALITY", None)
+        assert r["iters"] == ref.iters and r["stopped_by"] == "tol", (fused, r["iters"], ref.iters)
+        assert abs(r["q0"] - ref.q0) <= 1e-12 and abs(r["q_final"] - ref.q_final) <= 1e-12
+        assert np.max(np.abs(x - ref.x)) <= TOL64 * extent(u.xy)
+        outs[fused] = (x, y)
+    assert np.array_equal(outs["1"][0], outs["0"][0]) and np.array_equal(outs["1"][1], outs["0"][1])
