@@ -893,6 +893,104 @@ __global__ __launch_bounds__(BS) void k_colour2(const int32_t *__restrict__ list
 }
 
 // ---------------------------------------------------------------------------
+// All colours of one multicolour sweep (the in-place form, colours in
+// order) in one pass, tile by tile.  The tile stages its own rows and its
+// staged halo from src (the state at the start of the sweep) and updates in
+// LDS, colour by colour and in place, its own free rows and every halo
+// vertex whose new value one of them reads; it recomputes those the same way
+// their owner does, from the same values in the same order, so the bits are
+// those of the colour-by-colour sweep.  No two vertices of one colour are
+// adjacent, so the updates inside a colour do not race.  Own rows go to dst
+// (fixed ones unchanged).
+template <typename T, int BS, int W, int R, int MAP>
+__global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__ tile_ptr,
+                                                     const int64_t *__restrict__ halo_ptr,
+                                                     const int32_t *__restrict__ halo,
+                                                     const int64_t *__restrict__ upd_ptr,
+                                                     const uint16_t *__restrict__ urow,
+                                                     const uint16_t *__restrict__ uidx, int32_t C,
+                                                     const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst,
+                                                     const StopState *__restrict__ st) {
+    extern __shared__ unsigned char lds_raw[];
+    vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
+    if (st && st->done) return;
+    const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
+    const int tid = int(threadIdx.x);
+    const int32_t b = tile_ptr[tile], nown = tile_ptr[tile + 1] - b;
+    const int64_t hb = halo_ptr[tile];
+    const int32_t nh = int32_t(halo_ptr[tile + 1] - hb);
+    // this thread's updated rows (the tile's list, colour by colour): slot,
+    // colour and neighbour slots, held in registers for the whole pass
+    const int64_t *up = upd_ptr + int64_t(tile) * (C + 1);
+    uint32_t wd[R][W / 2];
+    int32_t row[R], colr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t e = up[0] + tid + BS * r;
+        colr[r] = -1;
+        row[r] = 0;
+        if (e < up[C]) {
+            load_slot_words<W>(uidx + e * W, wd[r]);
+            row[r] = urow[e];
+            int32_t c = 0;
+            while (up[c + 1] <= e) ++c;
+            colr[r] = c;
+        }
+    }
+    for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
+    for (int32_t j0 = tid; j0 < nh; j0 += 4 * BS) {
+        int32_t g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = j0 + q * BS < nh ? halo[hb + j0 + q * BS] : -1;
+        T hx[4], hy[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            hx[q] = T(0);
+            hy[q] = T(0);
+            if (g[q] >= 0) {
+                const vec2_t<T> h = src[g[q]];
+                hx[q] = h.x;
+                hy[q] = h.y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (g[q] >= 0) {
+                vec2_t<T> h;
+                h.x = hx[q];
+                h.y = hy[q];
+                sp[nown + j0 + q * BS] = h;
+            }
+    }
+    __syncthreads();
+    for (int32_t c = 0; c < C; ++c) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (colr[r] != c) continue;
+            T ax = T(0), ay = T(0);
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const uint32_t id = (wd[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
+                if (id != 0xFFFFu) {
+                    const vec2_t<T> p = sp[id];
+                    ax += p.x;
+                    ay += p.y;
+                    ++cnt;
+                }
+            }
+            if (cnt > 0) {
+                vec2_t<T> o;
+                o.x = ax / T(cnt);
+                o.y = ay / T(cnt);
+                sp[row[r]] = o;
+            }
+        }
+        __syncthreads();
+    }
+    for (int32_t i = tid; i < nown; i += BS) dst[b + i] = sp[i];
+}
+
 // Quality (Section 3.2) of one triangle: shortest / longest Euclidean edge.
 __device__ __forceinline__ double tri_quality(double xa, double ya, double xb, double yb, double xc,
                                               double yc) {
@@ -1311,6 +1409,15 @@ struct DeviceState {
         int64_t n_qc = 0;
     };
     std::deque<TBDev> tbs;       // uploaded temporal-blocking plans of the current version
+    struct MCDev {
+        int32_t ts = 0, l_cap = 0, u_cap = 0, tiles = 0, l_max = 0, colors = 0;
+        bool fits = false;
+        int32_t *tile_ptr = nullptr, *halo = nullptr;
+        int64_t *halo_ptr = nullptr, *upd_ptr = nullptr;
+        uint16_t *urow = nullptr, *uidx = nullptr;
+    };
+    std::deque<MCDev> mcs;       // uploaded one-pass multicolour plans of the current version
+    int mc_cfg[2] = {-2, -2};    // one-pass multicolour variant per precision; -1 = colour by colour; -2 = not tuned
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
     double *tw = nullptr;
     int32_t *trec = nullptr;
@@ -1432,6 +1539,8 @@ DeviceState &ensure_device(Mesh &M) {
         free_arrays(d);
         d->halos.clear();  // their arrays were in d->arrays
         d->tbs.clear();
+        d->mcs.clear();
+        d->mc_cfg[0] = d->mc_cfg[1] = -2;
         d->version = ~uint64_t(0);
         d->row_ptr = upload(d, M.row_ptr);
         d->col = upload(d, M.col);
@@ -2332,6 +2441,157 @@ int fused_stop_cfg(DeviceState &d, Mesh &M) {
     return ensure_tbq(d, M, tb_shape(c)) ? c : -1;
 }
 
+// One-pass multicolour variants: MC(id, tile size, staging cap, updated
+// rows per thread R (256 threads), map).
+#define LMS_MC_CONFIGS(MC)        \
+    MC(0, 128, 1024, 2, 16)       \
+    MC(1, 128, 1024, 2, 0)        \
+    MC(2, 256, 2048, 4, 16)       \
+    MC(3, 64, 512, 1, 16)
+constexpr int kNumMcConfigs = 4;
+
+struct MCShape {
+    int ts = 0, lcap = 0, r = 0, map = 0;
+};
+
+MCShape mc_shape(int cfg) {
+    switch (cfg) {
+#define MC(id, ts, lcap, r, map) \
+    case id:                     \
+        return MCShape{ts, lcap, r, map};
+        LMS_MC_CONFIGS(MC)
+#undef MC
+    }
+    return MCShape{};
+}
+
+const DeviceState::MCDev &ensure_mc(DeviceState &d, Mesh &M, const MCShape &t) {
+    for (const auto &h : d.mcs)
+        if (h.ts == t.ts && h.l_cap == t.lcap && h.u_cap == 256 * t.r) return h;
+    const Mesh::MCPlan &P = mc_plan(M, t.ts, t.lcap, 256 * t.r);
+    DeviceState::MCDev h;
+    h.ts = t.ts;
+    h.l_cap = t.lcap;
+    h.u_cap = 256 * t.r;
+    h.fits = P.fits;
+    h.tiles = P.tiles;
+    h.l_max = P.l_max;
+    h.colors = P.colors;
+    if (P.fits) {
+        h.tile_ptr = upload(&d, P.tile_ptr);
+        h.halo_ptr = upload(&d, P.halo_ptr);
+        h.halo = upload(&d, P.halo);
+        h.upd_ptr = upload(&d, P.upd_ptr);
+        h.urow = upload(&d, P.urow);
+        h.uidx = upload(&d, P.uidx);
+    }
+    d.mcs.push_back(h);
+    return d.mcs.back();
+}
+
+template <typename T>
+bool mc_usable(DeviceState &d, Mesh &M, int cfg) {
+    if (M.ell_w != 8 && M.ell_w != 12 && M.ell_w != 16) return false;
+    if (M.n_colors < 1 || M.n == 0) return false;
+    const DeviceState::MCDev &h = ensure_mc(d, M, mc_shape(cfg));
+    return h.fits && h.tiles > 0 && size_t(h.l_max) * sizeof(vec2_t<T>) <= size_t(64) * 1024;
+}
+
+// One multicolour sweep src -> dst in one pass of variant cfg.
+template <typename T>
+void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst,
+                   const StopState *st, hipStream_t s) {
+    const MCShape t = mc_shape(cfg);
+    const DeviceState::MCDev *h = nullptr;
+    for (const auto &x : d.mcs)
+        if (x.ts == t.ts && x.l_cap == t.lcap && x.u_cap == 256 * t.r) h = &x;
+    if (!h || !h->fits || h->colors != M.n_colors) fail(LMS_ERR_STATE, "one-pass multicolour variant without its plan");
+    if (size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024) fail(LMS_ERR_STATE, "multicolour plan too large");
+    const size_t lds = size_t(h->l_max) * sizeof(vec2_t<T>);
+    auto go = [&](auto kern) {
+        kern<<<h->tiles, 256, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx, h->colors,
+                                        src, dst, st);
+    };
+#define LMS_MC_W(W)                                                    \
+    switch (cfg) {                                                     \
+        case 0: go(k_colour_tiles<T, 256, W, 2, 16>); break;           \
+        case 1: go(k_colour_tiles<T, 256, W, 2, 0>); break;            \
+        case 2: go(k_colour_tiles<T, 256, W, 4, 16>); break;           \
+        case 3: go(k_colour_tiles<T, 256, W, 1, 16>); break;           \
+        default: fail(LMS_ERR_STATE, "unknown one-pass multicolour variant"); \
+    }
+    switch (M.ell_w) {
+        case 8:
+            LMS_MC_W(8)
+            break;
+        case 12:
+            LMS_MC_W(12)
+            break;
+        case 16:
+            LMS_MC_W(16)
+            break;
+        default:
+            fail(LMS_ERR_STATE, "no padded adjacency for the one-pass multicolour sweep");
+    }
+#undef LMS_MC_W
+    launch_check();
+}
+
+// Choose, per precision, between the colour-by-colour sweep and the one-pass
+// variants by timing one sweep of each (LMS_COLOUR_TILES=0 keeps colour by
+// colour; LMS_COLOUR_CONFIG=<id> forces a one-pass variant).
+template <typename T>
+void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_t s) {
+    const int pi = sizeof(T) == 8 ? 0 : 1;
+    if (d.mc_cfg[pi] != -2) return;
+    d.mc_cfg[pi] = -1;
+    if (!env_flag("LMS_COLOUR_TILES", true) || M.ell_w == 0) return;
+    if (const char *f = std::getenv("LMS_COLOUR_CONFIG")) {
+        const int c = std::atoi(f);
+        if (c < 0 || c >= kNumMcConfigs || !mc_usable<T>(d, M, c))
+            fail(LMS_ERR_ARG, "LMS_COLOUR_CONFIG names a one-pass multicolour variant this mesh cannot use");
+        d.mc_cfg[pi] = c;
+        return;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_CHECK(hipEventCreate(&e0));
+    hipError_t ce = hipEventCreate(&e1);
+    if (ce != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        HIP_CHECK(ce);
+    }
+    const int reps = M.n > (1 << 22) ? 3 : 8;
+    float best = 3.0e38f;
+    hipError_t err = hipSuccess;
+    for (int c = -1; c < kNumMcConfigs && err == hipSuccess; ++c) {
+        if (c >= 0 && !mc_usable<T>(d, M, c)) continue;
+        auto one = [&]() {
+            if (c < 0)
+                launch_colour_sweep2<T>(d, M, A, nullptr, s);
+            else
+                launch_mc_cfg<T>(c, d, M, A, B, nullptr, s);
+        };
+        one();
+        err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) one();
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess && ms < best) {
+            best = ms;
+            d.mc_cfg[pi] = c;
+        }
+        if (env_flag("LMS_VERBOSE", false))
+            std::fprintf(stderr, "[lms] multicolour %s: %.2f us per sweep\n",
+                         c < 0 ? "colour by colour" : ("one pass, variant " + std::to_string(c)).c_str(),
+                         double(ms) * 1000.0 / reps);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_CHECK(err);
+}
+
 // lms_smooth on the interleaved working copies: pack P_0 into both copies,
 // sweep back and forth between them (graph-captured), unpack the last one.
 template <typename T>
@@ -2343,11 +2603,24 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     const int tb = colour || o.check_quality ? -1 : d.tb_cfg[pi];
     vec2_t<T> *A = ensure_packed<T>(d, 0, M.n);
     vec2_t<T> *B = ensure_packed<T>(d, 1, M.n);
+    if (colour) tune_colour<T>(d, M, A, B, s);  // before the pack: it sweeps the working copies
+    const int mc = colour ? d.mc_cfg[pi] : -1;    // >= 0: multicolour in one pass per sweep, A/B ping-pong
+    const bool in_place = colour && mc < 0;
     const int nb = (M.n + 255) / 256;
-    k_pack<T><<<nb, 256, 0, s>>>(x, y, A, colour ? nullptr : B, M.n);
+    k_pack<T><<<nb, 256, 0, s>>>(x, y, A, in_place ? nullptr : B, M.n);
     launch_check();
     const std::string base = std::string("packed|") + (p == LMS_FP64 ? "f64" : "f32") + "|" + ptr_key(A) + "|" +
-                             ptr_key(B) + "|cfg" + std::to_string(cfg) + "|" + std::to_string(int(sch));
+                             ptr_key(B) + "|cfg" + std::to_string(cfg) + "|mc" + std::to_string(mc) + "|" +
+                             std::to_string(int(sch));
+    // one sweep src -> dst (Jacobi or one-pass multicolour), or colour by colour in place on A
+    auto sweep_once = [&](vec2_t<T> *src, vec2_t<T> *dst, const StopState *st, hipStream_t cs) {
+        if (in_place)
+            launch_colour_sweep2<T>(d, M, A, st, cs);
+        else if (colour)
+            launch_mc_cfg<T>(mc, d, M, src, dst, st, cs);
+        else
+            launch_sweep2_cfg<T>(cfg, d, M, src, dst, st, cs);
+    };
     int32_t iters = 0;
     bool in_b = false;  // the result sits in B
     const int small_rows = colour || o.check_quality ? 0 : small_batch_rows(M);
@@ -2380,17 +2653,10 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         const int32_t K = o.max_iters;
         if (K > 0)
             run_maybe_graph(d, "fixed|" + base + "|" + std::to_string(K), s, [&](hipStream_t cs) {
-                for (int32_t k = 0; k < K; ++k) {
-                    if (colour)
-                        launch_colour_sweep2<T>(d, M, A, nullptr, cs);
-                    else if (k % 2 == 0)
-                        launch_sweep2_cfg<T>(cfg, d, M, A, B, nullptr, cs);
-                    else
-                        launch_sweep2_cfg<T>(cfg, d, M, B, A, nullptr, cs);
-                }
+                for (int32_t k = 0; k < K; ++k) sweep_once(k % 2 == 0 ? A : B, k % 2 == 0 ? B : A, nullptr, cs);
             });
         iters = K;
-        in_b = !colour && K % 2 == 1;
+        in_b = !in_place && K % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
     } else if (const int fq = colour ? -1 : fused_stop_cfg<T>(d, M); fq >= 0) {
@@ -2441,13 +2707,8 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         const StopState h = run_stop_chunks(d, s, int64_t(o.max_iters) / kChunk + 2, [&]() {
             run_maybe_graph(d, key, s, [&](hipStream_t cs) {
                 for (int k = 0; k < kChunk; ++k) {
-                    vec2_t<T> *src = k % 2 == 0 ? A : B, *dst = k % 2 == 0 ? B : A;
-                    if (colour) {
-                        launch_colour_sweep2<T>(d, M, A, d.st, cs);
-                        dst = A;
-                    } else {
-                        launch_sweep2_cfg<T>(cfg, d, M, src, dst, d.st, cs);
-                    }
+                    vec2_t<T> *src = k % 2 == 0 ? A : B, *dst = in_place ? A : (k % 2 == 0 ? B : A);
+                    sweep_once(src, dst, d.st, cs);
                     launch_quality<T>(d, M, nullptr, nullptr, nullptr, d.st, cs, dst);
                     launch_stop(d, M, 0, o, cs);
                 }
@@ -2458,7 +2719,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         r.q0 = h.q0;
         r.q_final = h.q_last;
         r.last_dq = h.last_dq;
-        in_b = !colour && iters % 2 == 1;
+        in_b = !in_place && iters % 2 == 1;
     }
     k_unpack<T><<<nb, 256, 0, s>>>(in_b ? B : A, x, y, M.n);
     launch_check();

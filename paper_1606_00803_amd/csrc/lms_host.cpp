@@ -520,6 +520,7 @@ void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std
 
     M.halo_plans.clear();
     M.tb_plans.clear();
+    M.mc_plans.clear();
     M.ordering = kind;
     M.new2old = std::move(new2old);
     M.old2new = std::move(old2new);
@@ -930,6 +931,204 @@ void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
         }
     }
     P.q_fits = true;
+}
+
+const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
+    for (const auto &h : M.mc_plans)
+        if (h.ts == ts && h.l_cap == l_cap && h.u_cap == u_cap && h.version == M.version) return h;
+    if (M.ell_w <= 0) fail(LMS_ERR_STATE, "no padded adjacency for a multicolour tile plan");
+    if (ts <= 0 || l_cap < 1 || l_cap >= 0xFFFF || u_cap < 1) fail(LMS_ERR_ARG, "multicolour plan: bad tile size or cap");
+    const int32_t n = M.n, W = M.ell_w, C = M.n_colors;
+    const int64_t nominal = (int64_t(n) + ts - 1) / ts;
+    struct Part {
+        bool fits = true;
+        std::vector<int32_t> tile_end, halo, halo_n;
+        std::vector<int64_t> ucount;  // per tile and colour
+        std::vector<uint16_t> urow, uidx;
+        int32_t l_max = 0;
+    };
+    const int workers = host_threads(nominal);
+    std::vector<Part> parts(static_cast<size_t>(workers));
+    std::atomic<bool> give_up{false};
+    std::atomic<int64_t> all_own{0}, all_staged{0};
+    const int64_t sample = std::max<int64_t>(4096, int64_t(n) / 16);
+    parallel_runs(nominal, workers, [&](int w, int64_t first, int64_t last) {
+        Part &out = parts[size_t(w)];
+        SlotMap slots(size_t(l_cap) + size_t(W) + 1);
+        std::vector<int32_t> staged, upd, queue;
+        std::vector<uint8_t> in_upd_mark;  // parallel to staged: updated here
+        // Stage [b, e): own rows, the closure of updated rows, their
+        // neighbours; false when the staging area passes the cap.
+        auto try_tile = [&](int32_t b, int32_t e) {
+            slots.clear();
+            staged.clear();
+            in_upd_mark.clear();
+            queue.clear();
+            for (int32_t v = b; v < e; ++v) {
+                slots.insert(v, v - b);
+                staged.push_back(v);
+                in_upd_mark.push_back(M.fixed[size_t(v)] ? 0 : 1);
+                if (!M.fixed[size_t(v)]) queue.push_back(v);
+            }
+            if (int64_t(staged.size()) > l_cap) return false;
+            for (size_t qi = 0; qi < queue.size(); ++qi) {
+                if (int64_t(queue.size()) > u_cap) return false;
+                const int32_t v = queue[qi];
+                const int32_t cv = M.color[size_t(v)];
+                for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                    const int32_t u = M.col[size_t(j)];
+                    int32_t su = slots.get(u);
+                    if (su < 0) {
+                        su = int32_t(staged.size());
+                        slots.insert(u, su);
+                        staged.push_back(u);
+                        in_upd_mark.push_back(0);
+                        if (int64_t(staged.size()) > l_cap) return false;
+                    }
+                    // u is read by v: v needs u's value of this sweep when u's
+                    // colour comes first, so u is updated here too
+                    if (!M.fixed[size_t(u)] && M.color[size_t(u)] < cv && !in_upd_mark[size_t(su)]) {
+                        in_upd_mark[size_t(su)] = 1;
+                        queue.push_back(u);
+                    }
+                }
+            }
+            return int64_t(queue.size()) <= u_cap;
+        };
+        auto emit_tile = [&](int32_t b, int32_t e) {
+            const int32_t nown = e - b;
+            // slots: own rows, then the others in ascending id
+            std::vector<int32_t> others(staged.begin() + nown, staged.end());
+            std::sort(others.begin(), others.end());
+            for (size_t i = 0; i < others.size(); ++i) slots.set(others[i], nown + int32_t(i));
+            // updated rows by colour, ascending slot inside a colour
+            std::vector<std::vector<int32_t>> by_colour(size_t(std::max(C, 1)));
+            for (size_t i = 0; i < staged.size(); ++i)
+                if (in_upd_mark[i]) {
+                    const int32_t v = staged[i];
+                    by_colour[size_t(M.color[size_t(v)])].push_back(slots.get(v));
+                }
+            for (int32_t c = 0; c < C; ++c) {
+                auto &rows = by_colour[size_t(c)];
+                std::sort(rows.begin(), rows.end());
+                out.ucount.push_back(int64_t(rows.size()));
+                for (int32_t sl : rows) {
+                    const int32_t v = sl < nown ? b + sl : others[size_t(sl - nown)];
+                    out.urow.push_back(uint16_t(sl));
+                    const size_t base = out.uidx.size();
+                    out.uidx.resize(base + size_t(W), uint16_t(0xFFFF));
+                    for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                        const int32_t su = slots.get(M.col[size_t(j)]);
+                        if (su < 0) fail(LMS_ERR_STATE, "multicolour plan: neighbour not staged");
+                        out.uidx[base + size_t(j - M.row_ptr[v])] = uint16_t(su);
+                    }
+                }
+            }
+            out.tile_end.push_back(e);
+            out.halo.insert(out.halo.end(), others.begin(), others.end());
+            out.halo_n.push_back(int32_t(others.size()));
+            out.l_max = std::max(out.l_max, int32_t(staged.size()));
+        };
+        std::vector<std::pair<int32_t, int32_t>> todo;
+        for (int64_t t = first; t < last && out.fits; ++t) {
+            if (give_up.load(std::memory_order_relaxed)) {
+                out.fits = false;
+                break;
+            }
+            todo.emplace_back(int32_t(t * ts), int32_t(std::min<int64_t>(n, (t + 1) * ts)));
+            while (!todo.empty()) {
+                const auto [b, e] = todo.back();
+                todo.pop_back();
+                if (try_tile(b, e)) {
+                    emit_tile(b, e);
+                    const int64_t own = all_own.fetch_add(e - b) + (e - b);
+                    const int64_t st = all_staged.fetch_add(int64_t(staged.size())) + int64_t(staged.size());
+                    if (own > sample && st > kTBMaxStagedPerRow * own) {  // the same bound as temporal blocking
+                        out.fits = false;
+                        give_up.store(true, std::memory_order_relaxed);
+                        break;
+                    }
+                } else if (e - b > 1) {
+                    const int32_t mid = b + (e - b) / 2;
+                    todo.emplace_back(mid, e);
+                    todo.emplace_back(b, mid);
+                } else {
+                    out.fits = false;
+                    give_up.store(true, std::memory_order_relaxed);
+                    break;
+                }
+            }
+        }
+    });
+    Mesh::MCPlan P;
+    P.ts = ts;
+    P.l_cap = l_cap;
+    P.u_cap = u_cap;
+    P.colors = C;
+    for (const auto &q : parts) P.fits = P.fits && q.fits;
+    if (P.fits) {
+        P.tile_ptr.push_back(0);
+        P.halo_ptr.push_back(0);
+        P.upd_ptr.push_back(0);
+        for (auto &q : parts) {
+            P.l_max = std::max(P.l_max, q.l_max);
+            for (size_t t = 0; t < q.tile_end.size(); ++t) {
+                P.tile_ptr.push_back(q.tile_end[t]);
+                P.halo_ptr.push_back(P.halo_ptr.back() + q.halo_n[t]);
+            }
+            for (int64_t c : q.ucount) P.upd_ptr.push_back(P.upd_ptr.back() + c);
+            P.halo.insert(P.halo.end(), q.halo.begin(), q.halo.end());
+            P.urow.insert(P.urow.end(), q.urow.begin(), q.urow.end());
+            P.uidx.insert(P.uidx.end(), q.uidx.begin(), q.uidx.end());
+            q = Part{};
+        }
+        P.tiles = int32_t(P.tile_ptr.size() - 1);
+        // upd_ptr holds tiles*C counts' running sums: give each tile C+1 entries
+        std::vector<int64_t> up(size_t(P.tiles) * size_t(C + 1));
+        for (int32_t t = 0; t < P.tiles; ++t)
+            for (int32_t c = 0; c <= C; ++c) up[size_t(t) * size_t(C + 1) + size_t(c)] = P.upd_ptr[size_t(t) * size_t(C) + size_t(c)];
+        P.upd_ptr = std::move(up);
+        // self-check: tiles cover the rows; every own free row is updated once,
+        // in its colour; every updated row's slots name its neighbours in order
+        if (P.tile_ptr.back() != n) fail(LMS_ERR_STATE, "multicolour plan: tiles do not cover the rows");
+        for (int32_t t = 0; t < P.tiles; ++t) {
+            const int32_t b = P.tile_ptr[size_t(t)], e = P.tile_ptr[size_t(t) + 1], nown = e - b;
+            const int64_t hb = P.halo_ptr[size_t(t)];
+            const int32_t nst = nown + int32_t(P.halo_ptr[size_t(t) + 1] - hb);
+            auto global_of = [&](int32_t sl) { return sl < nown ? b + sl : P.halo[size_t(hb + sl - nown)]; };
+            std::vector<uint8_t> seen(size_t(nst), 0);
+            for (int32_t c = 0; c < C; ++c)
+                for (int64_t i = P.upd_ptr[size_t(t) * size_t(C + 1) + size_t(c)];
+                     i < P.upd_ptr[size_t(t) * size_t(C + 1) + size_t(c) + 1]; ++i) {
+                    const int32_t sl = P.urow[size_t(i)];
+                    if (sl >= nst || seen[size_t(sl)]) fail(LMS_ERR_STATE, "multicolour plan: bad updated row");
+                    seen[size_t(sl)] = 1;
+                    const int32_t v = global_of(sl);
+                    if (M.fixed[size_t(v)] || M.color[size_t(v)] != c) fail(LMS_ERR_STATE, "multicolour plan: colour");
+                    const int32_t deg = M.row_ptr[v + 1] - M.row_ptr[v];
+                    for (int32_t q = 0; q < W; ++q) {
+                        const uint16_t su = P.uidx[size_t(i) * size_t(W) + size_t(q)];
+                        if (q >= deg) {
+                            if (su != 0xFFFF) fail(LMS_ERR_STATE, "multicolour plan: padding slot in use");
+                            continue;
+                        }
+                        if (su >= nst || global_of(su) != M.col[size_t(M.row_ptr[v] + q)])
+                            fail(LMS_ERR_STATE, "multicolour plan: slot names the wrong vertex");
+                    }
+                }
+            for (int32_t sl = 0; sl < nown; ++sl)
+                if (!M.fixed[size_t(b + sl)] && !seen[size_t(sl)]) fail(LMS_ERR_STATE, "multicolour plan: own row missed");
+        }
+    } else {
+        P = Mesh::MCPlan{};
+        P.ts = ts;
+        P.l_cap = l_cap;
+        P.u_cap = u_cap;
+        P.fits = false;
+    }
+    P.version = M.version;
+    M.mc_plans.push_back(std::move(P));
+    return M.mc_plans.back();
 }
 
 // Locality profile of the current ordering: reuse distances of the sweep's

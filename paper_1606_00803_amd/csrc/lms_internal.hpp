@@ -133,6 +133,29 @@ struct Mesh {
     };
     std::deque<TBPlan> tb_plans;
 
+    // Tile plan of the multicolour sweep in one pass (all colours of one
+    // sweep, tile by tile, in LDS).  Tiles are row ranges (ts rows, halved
+    // until the staging area fits l_cap and the updated rows u_cap).  A tile updates its own free rows
+    // and every free halo vertex that an updated vertex of a higher colour
+    // reads (a closure along strictly decreasing colours), and stages the
+    // neighbours of everything it updates.  Local slots: own rows first,
+    // then the other staged vertices in ascending id.  The updated rows of
+    // tile t are listed by colour: upd_ptr[t*(C+1)+c] .. upd_ptr[t*(C+1)+c+1]
+    // index urow (their slot) and uidx (ell_w neighbour slots each, 0xFFFF
+    // past the row's end, in the row's order).
+    struct MCPlan {
+        int32_t ts = 0, l_cap = 0, u_cap = 0;
+        bool fits = true;
+        int32_t tiles = 0, l_max = 0, colors = 0;
+        std::vector<int32_t> tile_ptr;  // tiles+1
+        std::vector<int64_t> halo_ptr;  // tiles+1
+        std::vector<int32_t> halo;      // staged ids beyond the own rows
+        std::vector<int64_t> upd_ptr;   // tiles*(C+1)
+        std::vector<uint16_t> urow, uidx;
+        uint64_t version = ~uint64_t(0);
+    };
+    std::deque<MCPlan> mc_plans;
+
     // generation counter: bumped whenever the current labelling changes so
     // that device copies and captured graphs are refreshed
     uint64_t version = 0;
@@ -159,6 +182,7 @@ void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap);
 void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
+const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap);
 void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,
                    int32_t record_bytes, lms_reuse_stats &out);
 

@@ -691,3 +691,46 @@ def test_batched_stopping_rule_matches_the_oracle_on_the_union():
         assert np.max(np.abs(x - ref.x)) <= TOL64 * extent(u.xy)
         outs[fused] = (x, y)
     assert np.array_equal(outs["1"][0], outs["0"][0]) and np.array_equal(outs["1"][1], outs["0"][1])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["rdr", "bfs", "ori"])
+def test_one_pass_multicolour_same_bits_as_colour_by_colour(prec, kind):
+    # all colours of a sweep in one pass (tiles update their halo's lower
+    # colours themselves) against one launch per colour: the same bits, fixed
+    # sweep counts and the stopping rule; float64 also against the oracle
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    dt = torch.float64 if prec == "f64" else torch.float32
+    m = meshgen.jittered_grid(163, 149, seed=81, land_fraction=0.3)
+    top = oracle_topology(m)
+    cols = oord.colour_lists(oord.greedy_colouring(top))
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    try:
+        for kw in (dict(max_iters=1, check_quality=False), dict(max_iters=6, check_quality=False),
+                   dict(max_iters=2000, check_quality=True)):
+            os.environ["LMS_COLOUR_TILES"] = "0"
+            rx, ry, rr, _ = run_library(m, kind, kw["max_iters"], dtype=dt, M=M, scheme="multicolor",
+                                        check_quality=kw["check_quality"])
+            os.environ.pop("LMS_COLOUR_TILES")
+            ran = 0
+            for cfg in range(4):
+                os.environ["LMS_COLOUR_CONFIG"] = str(cfg)
+                try:
+                    x, y, r, _ = run_library(m, kind, kw["max_iters"], dtype=dt, M=M, scheme="multicolor",
+                                             check_quality=kw["check_quality"])
+                except lms.LmsError as e:            # the plan gave up (halo too wide)
+                    assert e.status == 1 and "cannot use" in str(e)
+                    continue
+                finally:
+                    os.environ.pop("LMS_COLOUR_CONFIG", None)
+                ran += 1
+                assert r["iters"] == rr["iters"] and r["stopped_by"] == rr["stopped_by"], (cfg, kw)
+                assert np.array_equal(x, rx) and np.array_equal(y, ry), (cfg, kw)
+            assert ran >= 2, kind
+            if prec == "f64" and not kw["check_quality"]:
+                ex, ey = osm.multicolor(top, cols[0], cols[1], m.x, m.y, kw["max_iters"])
+                assert np.max(np.abs(rx - ex)) <= TOL64 * extent(m.xy)
+    finally:
+        os.environ.pop("LMS_COLOUR_TILES", None)
+        os.environ.pop("LMS_COLOUR_CONFIG", None)
