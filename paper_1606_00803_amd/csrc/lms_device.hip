@@ -902,7 +902,12 @@ __global__ __launch_bounds__(BS) void k_colour2(const int32_t *__restrict__ list
 // those of the colour-by-colour sweep.  No two vertices of one colour are
 // adjacent, so the updates inside a colour do not race.  Own rows go to dst
 // (fixed ones unchanged).
-template <typename T, int BS, int W, int R, int MAP>
+//
+// QUAL (the stopping rule, Section 5.1): the pass first evaluates the
+// quality of the state it sweeps from over the tile's triangles (their
+// corners are all staged) into qpart[tile]; its depth (1, or 0 once all
+// sweeps are done: quality only) comes from the device state.
+template <typename T, int BS, int W, int R, int MAP, bool QUAL>
 __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__ tile_ptr,
                                                      const int64_t *__restrict__ halo_ptr,
                                                      const int32_t *__restrict__ halo,
@@ -910,10 +915,20 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
                                                      const uint16_t *__restrict__ urow,
                                                      const uint16_t *__restrict__ uidx, int32_t C,
                                                      const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst,
-                                                     const StopState *__restrict__ st) {
+                                                     const StopState *__restrict__ st,
+                                                     const int64_t *__restrict__ qtri_ptr,
+                                                     const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
+                                                     int32_t max_iters) {
     extern __shared__ unsigned char lds_raw[];
+    __shared__ double s_red[BS / 64];
+    __shared__ double s_rcp[QUAL ? 65 : 1];
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
     if (st && st->done) return;
+    int32_t depth = 1;
+    if constexpr (QUAL) {
+        depth = min(1, max_iters - st->swept);
+        for (int c = int(threadIdx.x); c <= 64; c += BS) s_rcp[c] = c == 0 ? 0.0 : 1.0 / double(c);
+    }
     const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
     const int tid = int(threadIdx.x);
     const int32_t b = tile_ptr[tile], nown = tile_ptr[tile + 1] - b;
@@ -963,6 +978,25 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
             }
     }
     __syncthreads();
+    if constexpr (QUAL) {
+        // quality of the source state: the tile's triangles, from LDS
+        double acc = 0.0;
+        for (int64_t t = qtri_ptr[tile] + tid; t < qtri_ptr[tile + 1]; t += BS) {
+            const uint32_t w0 = qtri[3 * t], w1 = qtri[3 * t + 1], w2 = qtri[3 * t + 2];
+            const vec2_t<T> pa = sp[w0 & 0xFFFFu], pb = sp[w0 >> 16], pc = sp[w1 & 0xFFFFu];
+            const double q = tri_quality(double(pa.x), double(pa.y), double(pb.x), double(pb.y), double(pc.x),
+                                         double(pc.y));
+            const uint32_t ca = w1 >> 16, cb = w2 & 0xFFFFu, cc = w2 >> 16;
+            const double ra = ca <= 64 ? s_rcp[ca] : 1.0 / double(ca);
+            const double rb = cb <= 64 ? s_rcp[cb] : 1.0 / double(cb);
+            const double rc = cc <= 64 ? s_rcp[cc] : 1.0 / double(cc);
+            acc += q * (ra + rb + rc);
+        }
+        const double sum = block_sum<BS>(acc, s_red);
+        if (tid == 0) qpart[tile] = sum;
+        if (depth == 0) return;  // all sweeps done: the state was evaluated only
+        __syncthreads();
+    }
     for (int32_t c = 0; c < C; ++c) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1415,6 +1449,13 @@ struct DeviceState {
         int32_t *tile_ptr = nullptr, *halo = nullptr;
         int64_t *halo_ptr = nullptr, *upd_ptr = nullptr;
         uint16_t *urow = nullptr, *uidx = nullptr;
+        bool q_ready = false, q_fits = false;
+        int64_t *qtri_ptr = nullptr;
+        uint32_t *qtri = nullptr;
+        double *qpart = nullptr, *qpart2 = nullptr, *qc_w = nullptr;
+        int32_t *qc_ids = nullptr;
+        int32_t nsum = 0;
+        int64_t n_qc = 0;
     };
     std::deque<MCDev> mcs;       // uploaded one-pass multicolour plans of the current version
     int mc_cfg[2] = {-2, -2};    // one-pass multicolour variant per precision; -1 = colour by colour; -2 = not tuned
@@ -2417,15 +2458,21 @@ StopState run_stop_chunks(DeviceState &d, hipStream_t s, int64_t max_chunks, F i
 
 // The stopping rule after one quality-fused pass: the tiles' sums, in one or
 // two fixed-shape levels, then the rule.
-void launch_stop_tb(const DeviceState &d, const DeviceState::TBDev &h, int32_t kp, int32_t max_iters,
-                    const StopArgs &sa, hipStream_t s) {
-    if (h.nsum > 0) {
-        k_sum_tiles<<<h.nsum, 256, 0, s>>>(h.qpart, h.tiles, kp, d.st, max_iters, h.qpart2);
-        k_stop_tb<1024><<<1, 1024, 0, s>>>(h.qpart2, h.nsum, kp, d.st, sa);
+void launch_stop_tiles(const DeviceState &d, double *qpart, int32_t tiles, double *qpart2, int32_t nsum, int32_t kp,
+                       int32_t max_iters, const StopArgs &sa, hipStream_t s) {
+    if (nsum > 0) {
+        k_sum_tiles<<<nsum, 256, 0, s>>>(qpart, tiles, kp, d.st, max_iters, qpart2);
+        k_stop_tb<1024><<<1, 1024, 0, s>>>(qpart2, nsum, kp, d.st, sa);
     } else {
-        k_stop_tb<1024><<<1, 1024, 0, s>>>(h.qpart, h.tiles, kp, d.st, sa);
+        k_stop_tb<1024><<<1, 1024, 0, s>>>(qpart, tiles, kp, d.st, sa);
     }
 }
+
+void launch_stop_tb(const DeviceState &d, const DeviceState::TBDev &h, int32_t kp, int32_t max_iters,
+                    const StopArgs &sa, hipStream_t s) {
+    launch_stop_tiles(d, h.qpart, h.tiles, h.qpart2, h.nsum, kp, max_iters, sa, s);
+}
+
 
 // Passes per captured chunk of the quality-fused stopping rule (even, so that
 // every chunk starts from copy A).
@@ -2500,25 +2547,30 @@ bool mc_usable(DeviceState &d, Mesh &M, int cfg) {
 // One multicolour sweep src -> dst in one pass of variant cfg.
 template <typename T>
 void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst,
-                   const StopState *st, hipStream_t s) {
+                   const StopState *st, hipStream_t s, bool qual = false, int32_t max_iters = 0) {
     const MCShape t = mc_shape(cfg);
     const DeviceState::MCDev *h = nullptr;
     for (const auto &x : d.mcs)
         if (x.ts == t.ts && x.l_cap == t.lcap && x.u_cap == 256 * t.r) h = &x;
     if (!h || !h->fits || h->colors != M.n_colors) fail(LMS_ERR_STATE, "one-pass multicolour variant without its plan");
     if (size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024) fail(LMS_ERR_STATE, "multicolour plan too large");
+    if (qual && (!h->q_ready || !h->q_fits || !st)) fail(LMS_ERR_STATE, "quality-fused multicolour pass without its plan");
     const size_t lds = size_t(h->l_max) * sizeof(vec2_t<T>);
-    auto go = [&](auto kern) {
-        kern<<<h->tiles, 256, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx, h->colors,
-                                        src, dst, st);
+    auto go = [&](auto plain, auto fused) {
+        if (qual)
+            fused<<<h->tiles, 256, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
+                                             h->colors, src, dst, st, h->qtri_ptr, h->qtri, h->qpart, max_iters);
+        else
+            plain<<<h->tiles, 256, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
+                                             h->colors, src, dst, st, nullptr, nullptr, nullptr, 0);
     };
-#define LMS_MC_W(W)                                                    \
-    switch (cfg) {                                                     \
-        case 0: go(k_colour_tiles<T, 256, W, 2, 16>); break;           \
-        case 1: go(k_colour_tiles<T, 256, W, 2, 0>); break;            \
-        case 2: go(k_colour_tiles<T, 256, W, 4, 16>); break;           \
-        case 3: go(k_colour_tiles<T, 256, W, 1, 16>); break;           \
-        default: fail(LMS_ERR_STATE, "unknown one-pass multicolour variant"); \
+#define LMS_MC_W(W)                                                                                    \
+    switch (cfg) {                                                                                     \
+        case 0: go(k_colour_tiles<T, 256, W, 2, 16, false>, k_colour_tiles<T, 256, W, 2, 16, true>); break; \
+        case 1: go(k_colour_tiles<T, 256, W, 2, 0, false>, k_colour_tiles<T, 256, W, 2, 0, true>); break;   \
+        case 2: go(k_colour_tiles<T, 256, W, 4, 16, false>, k_colour_tiles<T, 256, W, 4, 16, true>); break; \
+        case 3: go(k_colour_tiles<T, 256, W, 1, 16, false>, k_colour_tiles<T, 256, W, 1, 16, true>); break; \
+        default: fail(LMS_ERR_STATE, "unknown one-pass multicolour variant");                           \
     }
     switch (M.ell_w) {
         case 8:
@@ -2590,6 +2642,33 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_CHECK(err);
+}
+
+// The quality-fused form of a one-pass multicolour plan (false when some
+// vertex lies in more than 65535 triangles).
+bool ensure_mcq(DeviceState &d, Mesh &M, const MCShape &t) {
+    DeviceState::MCDev *h = nullptr;
+    for (auto &x : d.mcs)
+        if (x.ts == t.ts && x.l_cap == t.lcap && x.u_cap == 256 * t.r) h = &x;
+    if (!h || !h->fits) fail(LMS_ERR_STATE, "quality-fused multicolour pass without its tile plan");
+    if (h->q_ready) return h->q_fits;
+    Mesh::MCPlan *P = nullptr;
+    for (auto &p : M.mc_plans)
+        if (p.ts == t.ts && p.l_cap == t.lcap && p.u_cap == 256 * t.r && p.version == M.version) P = &p;
+    if (!P) fail(LMS_ERR_STATE, "multicolour tile plan missing on the host");
+    mc_quality_plan(M, *P);
+    h->q_ready = true;
+    h->q_fits = P->q_fits;
+    if (!h->q_fits) return false;
+    h->qtri_ptr = upload(&d, P->qtri_ptr);
+    h->qtri = upload(&d, P->qtri);
+    h->qc_ids = upload(&d, P->qc_ids);
+    h->qc_w = upload(&d, P->qc_w);
+    h->n_qc = int64_t(P->qc_w.size());
+    h->qpart = upload(&d, std::vector<double>(size_t(std::max(h->tiles, 1)), 0.0));
+    h->nsum = h->tiles > 8192 ? std::min(1024, (h->tiles + 2047) / 2048) : 0;
+    h->qpart2 = upload(&d, std::vector<double>(size_t(std::max(h->nsum, 1)), 0.0));
+    return true;
 }
 
 // lms_smooth on the interleaved working copies: pack P_0 into both copies,
@@ -2692,6 +2771,42 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         vec2_t<T> *fsrc = hs.src == 0 ? A : B, *fother = hs.src == 0 ? B : A;
         if (hs.redo > 0) launch_tb_cfg<T>(fq, d, M, fsrc, fother, hs.redo, s);
         in_b = (hs.redo > 0 ? fother : fsrc) == B;
+        iters = hs.iters;
+        r.stopped_by = hs.stopped_by;
+        r.q0 = hs.q0;
+        r.q_final = hs.q_last;
+        r.last_dq = hs.last_dq;
+    } else if (colour && mc >= 0 && env_flag("LMS_FUSED_QUALITY", true) && ensure_mcq(d, M, mc_shape(mc))) {
+        // multicolour, one pass per sweep, each pass evaluating the quality
+        // of the state it sweeps from: a stop is at the source copy of the
+        // pass that evaluated it
+        const MCShape t = mc_shape(mc);
+        const DeviceState::MCDev *h = nullptr;
+        for (const auto &xh : d.mcs)
+            if (xh.ts == t.ts && xh.l_cap == t.lcap && xh.u_cap == 256 * t.r) h = &xh;
+        k_stop_reset<<<1, 64, 0, s>>>(d.st);
+        k_qconst<T><<<1, 256, 0, s>>>(h->qc_ids, h->qc_w, h->n_qc, A, d.st);
+        launch_check();
+        const bool use_prev = !std::isnan(o.q_prev);
+        const std::string key = "stopmc|" + base + "|" + dbl_key(o.tol) + "|" + dbl_key(o.goal) + "|" +
+                                std::to_string(o.max_iters);
+        const StopState hs = run_stop_chunks(d, s, (int64_t(o.max_iters) + 1) / kFusedChunk + 2, [&]() {
+            run_maybe_graph(d, key, s, [&](hipStream_t cs) {
+                for (int q = 0; q < kFusedChunk; ++q) {
+                    StopArgs sa{};
+                    sa.inv_n = 1.0 / double(M.n);
+                    sa.tol = o.tol;
+                    sa.goal = o.goal;
+                    sa.q_prev_given = use_prev ? o.q_prev : 0.0;
+                    sa.use_q_prev = use_prev ? 1 : 0;
+                    sa.max_iters = o.max_iters;
+                    sa.src_index = q % 2;
+                    launch_mc_cfg<T>(mc, d, M, q % 2 == 0 ? A : B, q % 2 == 0 ? B : A, d.st, cs, true, o.max_iters);
+                    launch_stop_tiles(d, h->qpart, h->tiles, h->qpart2, h->nsum, 1, o.max_iters, sa, cs);
+                }
+            });
+        });
+        in_b = hs.src == 1;
         iters = hs.iters;
         r.stopped_by = hs.stopped_by;
         r.q0 = hs.q0;

@@ -854,16 +854,22 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
     return M.tb_plans.back();
 }
 
-void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
-    if (P.q_built) return;
-    if (!P.fits || P.version != M.version) fail(LMS_ERR_STATE, "quality plan of a stale or unusable tile plan");
+namespace {
+
+// Triangle records of a tile plan for the quality evaluated inside the sweep
+// passes.  Every triangle with a free corner belongs to the tile owning its
+// smallest free corner; slot_of(tile, v) gives a staged corner's slot (every
+// corner is staged: the others are neighbours of that free corner).
+// Records: slots a | b<<16, c | |T(a)|<<16, |T(b)| | |T(c)|<<16.  Triangles
+// with all corners fixed are listed apart with their weights.  False when a
+// triangle count exceeds 16 bits.
+template <class SlotOf>
+bool tile_quality_records(const Mesh &M, int32_t tiles, const std::vector<int32_t> &tile_ptr, SlotOf slot_of,
+                          std::vector<int64_t> &qtri_ptr, std::vector<uint32_t> &qtri, std::vector<int32_t> &qc_ids,
+                          std::vector<double> &qc_w) {
     const int64_t T = M.T;
-    const int32_t k = P.k;
-    P.q_built = true;
-    P.q_fits = false;
     for (int32_t v = 0; v < M.n; ++v)
-        if (M.tcount0[size_t(v)] > 0xFFFF) return;  // counts do not fit 16 bits
-    // owning tile and record of every triangle with a free corner (-1: all fixed)
+        if (M.tcount0[size_t(v)] > 0xFFFF) return false;
     std::vector<int32_t> owner(size_t(T), -1);
     std::vector<uint32_t> rec(size_t(3) * size_t(T), 0u);
     parallel_runs(T, host_threads(T / 256), [&](int, int64_t first, int64_t last) {
@@ -874,22 +880,13 @@ void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
                 if (!M.fixed[size_t(v)] && (own < 0 || v < own)) own = v;
             if (own < 0) continue;
             const int32_t tile =
-                int32_t(std::upper_bound(P.tile_ptr.begin(), P.tile_ptr.end(), own) - P.tile_ptr.begin()) - 1;
-            const int32_t b = P.tile_ptr[size_t(tile)], e = P.tile_ptr[size_t(tile) + 1];
-            const int32_t *r = P.ring.data() + size_t(tile) * size_t(k + 1);
-            const int32_t *h1 = P.halo.data() + P.halo_ptr[size_t(tile)];
-            const int32_t n1 = r[1] - r[0];
+                int32_t(std::upper_bound(tile_ptr.begin(), tile_ptr.end(), own) - tile_ptr.begin()) - 1;
             uint32_t slot[3], cnt[3];
             for (int q = 0; q < 3; ++q) {
-                const int32_t v = c3[q];
-                if (v >= b && v < e) {
-                    slot[q] = uint32_t(v - b);
-                } else {
-                    const int32_t *it = std::lower_bound(h1, h1 + n1, v);
-                    if (it == h1 + n1 || *it != v) fail(LMS_ERR_STATE, "quality plan: corner not staged");
-                    slot[q] = uint32_t(r[0] + (it - h1));
-                }
-                cnt[q] = uint32_t(M.tcount0[size_t(M.new2old[size_t(v)])]);
+                const int32_t sl = slot_of(tile, c3[q]);
+                if (sl < 0) fail(LMS_ERR_STATE, "quality plan: corner not staged");
+                slot[q] = uint32_t(sl);
+                cnt[q] = uint32_t(M.tcount0[size_t(M.new2old[size_t(c3[q])])]);
             }
             owner[size_t(t)] = tile;
             rec[size_t(3 * t)] = slot[0] | (slot[1] << 16);
@@ -898,29 +895,50 @@ void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
         }
     });
     // group by tile (stable: ascending triangle index inside a tile)
-    P.qtri_ptr.assign(size_t(P.tiles) + 1, 0);
-    P.qc_ids.clear();
-    P.qc_w.clear();
+    qtri_ptr.assign(size_t(tiles) + 1, 0);
+    qc_ids.clear();
+    qc_w.clear();
     for (int64_t t = 0; t < T; ++t) {
         if (owner[size_t(t)] >= 0) {
-            P.qtri_ptr[size_t(owner[size_t(t)]) + 1]++;
+            qtri_ptr[size_t(owner[size_t(t)]) + 1]++;
         } else {
-            const int32_t a = M.ta[size_t(t)], bb = M.tb[size_t(t)], c = M.tc[size_t(t)];
-            P.qc_ids.insert(P.qc_ids.end(), {a, bb, c});
-            P.qc_w.push_back(M.tw[size_t(t)]);
+            qc_ids.insert(qc_ids.end(), {M.ta[size_t(t)], M.tb[size_t(t)], M.tc[size_t(t)]});
+            qc_w.push_back(M.tw[size_t(t)]);
         }
     }
-    for (int32_t i = 0; i < P.tiles; ++i) P.qtri_ptr[size_t(i) + 1] += P.qtri_ptr[size_t(i)];
-    resize_or_fail(P.qtri, size_t(3) * size_t(P.qtri_ptr.back()));
-    std::vector<int64_t> fill(P.qtri_ptr.begin(), P.qtri_ptr.end() - 1);
+    for (int32_t i = 0; i < tiles; ++i) qtri_ptr[size_t(i) + 1] += qtri_ptr[size_t(i)];
+    resize_or_fail(qtri, size_t(3) * size_t(qtri_ptr.back()));
+    std::vector<int64_t> fill(qtri_ptr.begin(), qtri_ptr.end() - 1);
     for (int64_t t = 0; t < T; ++t) {
         const int32_t o = owner[size_t(t)];
         if (o < 0) continue;
         const int64_t at = fill[size_t(o)]++;
-        for (int q = 0; q < 3; ++q) P.qtri[size_t(3 * at + q)] = rec[size_t(3 * t + q)];
+        for (int q = 0; q < 3; ++q) qtri[size_t(3 * at + q)] = rec[size_t(3 * t + q)];
     }
-    // self-check: every triangle counted once, its slots inside own + ring 1
-    if (P.qtri_ptr.back() + int64_t(P.qc_w.size()) != T) fail(LMS_ERR_STATE, "quality plan: triangle count");
+    if (qtri_ptr.back() + int64_t(qc_w.size()) != T) fail(LMS_ERR_STATE, "quality plan: triangle count");
+    return true;
+}
+
+}  // namespace
+
+void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
+    if (P.q_built) return;
+    if (!P.fits || P.version != M.version) fail(LMS_ERR_STATE, "quality plan of a stale or unusable tile plan");
+    const int32_t k = P.k;
+    P.q_built = true;
+    // a corner outside the own rows sits in ring 1 (sorted ascending)
+    auto slot_of = [&](int32_t tile, int32_t v) -> int32_t {
+        const int32_t b = P.tile_ptr[size_t(tile)], e = P.tile_ptr[size_t(tile) + 1];
+        if (v >= b && v < e) return v - b;
+        const int32_t *r = P.ring.data() + size_t(tile) * size_t(k + 1);
+        const int32_t *h1 = P.halo.data() + P.halo_ptr[size_t(tile)];
+        const int32_t n1 = r[1] - r[0];
+        const int32_t *it = std::lower_bound(h1, h1 + n1, v);
+        return it == h1 + n1 || *it != v ? -1 : r[0] + int32_t(it - h1);
+    };
+    P.q_fits = tile_quality_records(M, P.tiles, P.tile_ptr, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
+    if (!P.q_fits) return;
+    // self-check: slots inside own + ring 1, counts non-zero
     for (int32_t i = 0; i < P.tiles; ++i) {
         const int32_t *r = P.ring.data() + size_t(i) * size_t(k + 1);
         for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t) {
@@ -930,7 +948,33 @@ void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
                 fail(LMS_ERR_STATE, "quality plan: record out of range");
         }
     }
-    P.q_fits = true;
+}
+
+void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P) {
+    if (P.q_built) return;
+    if (!P.fits || P.version != M.version) fail(LMS_ERR_STATE, "quality plan of a stale or unusable tile plan");
+    P.q_built = true;
+    // a corner outside the own rows sits in the tile's staged list (ascending)
+    auto slot_of = [&](int32_t tile, int32_t v) -> int32_t {
+        const int32_t b = P.tile_ptr[size_t(tile)], e = P.tile_ptr[size_t(tile) + 1];
+        if (v >= b && v < e) return v - b;
+        const int32_t *h = P.halo.data() + P.halo_ptr[size_t(tile)];
+        const int32_t nh = int32_t(P.halo_ptr[size_t(tile) + 1] - P.halo_ptr[size_t(tile)]);
+        const int32_t *it = std::lower_bound(h, h + nh, v);
+        return it == h + nh || *it != v ? -1 : (e - b) + int32_t(it - h);
+    };
+    P.q_fits = tile_quality_records(M, P.tiles, P.tile_ptr, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
+    if (!P.q_fits) return;
+    for (int32_t i = 0; i < P.tiles; ++i) {
+        const uint32_t nst =
+            uint32_t(P.tile_ptr[size_t(i) + 1] - P.tile_ptr[size_t(i)] + P.halo_ptr[size_t(i) + 1] - P.halo_ptr[size_t(i)]);
+        for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t) {
+            const uint32_t w0 = P.qtri[size_t(3 * t)], w1 = P.qtri[size_t(3 * t + 1)], w2 = P.qtri[size_t(3 * t + 2)];
+            if ((w0 & 0xFFFFu) >= nst || (w0 >> 16) >= nst || (w1 & 0xFFFFu) >= nst || (w1 >> 16) == 0 ||
+                (w2 & 0xFFFFu) == 0 || (w2 >> 16) == 0)
+                fail(LMS_ERR_STATE, "quality plan: record out of range");
+        }
+    }
 }
 
 const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {

@@ -152,6 +152,13 @@ struct Mesh {
         std::vector<int32_t> halo;      // staged ids beyond the own rows
         std::vector<int64_t> upd_ptr;   // tiles*(C+1)
         std::vector<uint16_t> urow, uidx;
+        // quality evaluated in the pass (as for TBPlan, slots into this
+        // plan's staging area); filled by mc_quality_plan
+        bool q_built = false, q_fits = false;
+        std::vector<int64_t> qtri_ptr;
+        std::vector<uint32_t> qtri;
+        std::vector<int32_t> qc_ids;
+        std::vector<double> qc_w;
         uint64_t version = ~uint64_t(0);
     };
     std::deque<MCPlan> mc_plans;
@@ -183,6 +190,7 @@ const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap);
 void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
 const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap);
+void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P);
 void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,
                    int32_t record_bytes, lms_reuse_stats &out);
 

@@ -708,17 +708,19 @@ def test_one_pass_multicolour_same_bits_as_colour_by_colour(prec, kind):
     M = lms.Mesh.build_csr(m.n, m.tri)
     try:
         for kw in (dict(max_iters=1, check_quality=False), dict(max_iters=6, check_quality=False),
-                   dict(max_iters=2000, check_quality=True)):
+                   dict(max_iters=2000, check_quality=True), dict(max_iters=0, check_quality=True),
+                   dict(max_iters=3, check_quality=True), dict(max_iters=2000, check_quality=True, goal=0.0)):
+            extra = {k: v for k, v in kw.items() if k not in ("max_iters", "check_quality")}
             os.environ["LMS_COLOUR_TILES"] = "0"
             rx, ry, rr, _ = run_library(m, kind, kw["max_iters"], dtype=dt, M=M, scheme="multicolor",
-                                        check_quality=kw["check_quality"])
+                                        check_quality=kw["check_quality"], **extra)
             os.environ.pop("LMS_COLOUR_TILES")
             ran = 0
             for cfg in range(4):
                 os.environ["LMS_COLOUR_CONFIG"] = str(cfg)
                 try:
                     x, y, r, _ = run_library(m, kind, kw["max_iters"], dtype=dt, M=M, scheme="multicolor",
-                                             check_quality=kw["check_quality"])
+                                             check_quality=kw["check_quality"], **extra)
                 except lms.LmsError as e:            # the plan gave up (halo too wide)
                     assert e.status == 1 and "cannot use" in str(e)
                     continue
@@ -727,6 +729,9 @@ def test_one_pass_multicolour_same_bits_as_colour_by_colour(prec, kind):
                 ran += 1
                 assert r["iters"] == rr["iters"] and r["stopped_by"] == rr["stopped_by"], (cfg, kw)
                 assert np.array_equal(x, rx) and np.array_equal(y, ry), (cfg, kw)
+                for key in ("q0", "q_final", "last_dq"):         # fused quality vs the separate pass
+                    a, b = r[key], rr[key]
+                    assert (math.isnan(a) and math.isnan(b)) or abs(a - b) <= 1e-12, (cfg, kw, key)
             assert ran >= 2, kind
             if prec == "f64" and not kw["check_quality"]:
                 ex, ey = osm.multicolor(top, cols[0], cols[1], m.x, m.y, kw["max_iters"])
