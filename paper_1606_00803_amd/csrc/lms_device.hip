@@ -2111,6 +2111,30 @@ vec2_t<T> *ensure_packed(DeviceState &d, int which, int32_t n) {
     return static_cast<vec2_t<T> *>(d.pk[pi][which]);
 }
 
+// One-pass multicolour variants: MC(id, tile size, staging cap, updated
+// rows per thread R (256 threads), map).
+#define LMS_MC_CONFIGS(MC)        \
+    MC(0, 128, 1024, 2, 16)       \
+    MC(1, 128, 1024, 2, 0)        \
+    MC(2, 256, 2048, 4, 16)       \
+    MC(3, 64, 512, 1, 16)
+constexpr int kNumMcConfigs = 4;
+
+struct MCShape {
+    int ts = 0, lcap = 0, r = 0, map = 0;
+};
+
+MCShape mc_shape(int cfg) {
+    switch (cfg) {
+#define MC(id, ts, lcap, r, map) \
+    case id:                     \
+        return MCShape{ts, lcap, r, map};
+        LMS_MC_CONFIGS(MC)
+#undef MC
+    }
+    return MCShape{};
+}
+
 // Meshes from this many rows on drop, after each tuning, the tile plans that
 // no tuned precision's chosen variants use (host and device): there each plan
 // costs ~20-40 bytes per row, and the tuner builds a dozen.
@@ -2154,11 +2178,36 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
                               static_cast<const void *>(it->halo), static_cast<const void *>(it->halo_ptr),
                               static_cast<const void *>(it->lidx_ptr), static_cast<const void *>(it->lidx),
                               static_cast<const void *>(it->qtri_ptr), static_cast<const void *>(it->qtri),
-                              static_cast<const void *>(it->qpart), static_cast<const void *>(it->qc_ids),
-                              static_cast<const void *>(it->qc_w)})
+                              static_cast<const void *>(it->qpart), static_cast<const void *>(it->qpart2),
+                              static_cast<const void *>(it->qc_ids), static_cast<const void *>(it->qc_w)})
             free_array(d, p);
         it = d.tbs.erase(it);
     }
+    // one-pass multicolour plans: keep the tuned precisions' choices
+    auto keep_mc = [&](int32_t ts, int32_t l_cap, int32_t u_cap) {
+        for (int pi = 0; pi < 2; ++pi)
+            if (d.mc_cfg[pi] >= 0) {
+                const MCShape t = mc_shape(d.mc_cfg[pi]);
+                if (t.ts == ts && t.lcap == l_cap && 256 * t.r == u_cap) return true;
+            }
+        return false;
+    };
+    for (auto it = d.mcs.begin(); it != d.mcs.end();) {
+        if (keep_mc(it->ts, it->l_cap, it->u_cap)) {
+            ++it;
+            continue;
+        }
+        for (const void *p : {static_cast<const void *>(it->tile_ptr), static_cast<const void *>(it->halo),
+                              static_cast<const void *>(it->halo_ptr), static_cast<const void *>(it->upd_ptr),
+                              static_cast<const void *>(it->urow), static_cast<const void *>(it->uidx),
+                              static_cast<const void *>(it->qtri_ptr), static_cast<const void *>(it->qtri),
+                              static_cast<const void *>(it->qpart), static_cast<const void *>(it->qpart2),
+                              static_cast<const void *>(it->qc_ids), static_cast<const void *>(it->qc_w)})
+            free_array(d, p);
+        it = d.mcs.erase(it);
+    }
+    for (auto it = M.mc_plans.begin(); it != M.mc_plans.end();)
+        it = keep_mc(it->ts, it->l_cap, it->u_cap) ? std::next(it) : M.mc_plans.erase(it);
     for (auto it = M.halo_plans.begin(); it != M.halo_plans.end();)
         it = keep_ts(it->ts) ? std::next(it) : M.halo_plans.erase(it);
     for (auto it = M.tb_plans.begin(); it != M.tb_plans.end();)
@@ -2488,30 +2537,6 @@ int fused_stop_cfg(DeviceState &d, Mesh &M) {
     return ensure_tbq(d, M, tb_shape(c)) ? c : -1;
 }
 
-// One-pass multicolour variants: MC(id, tile size, staging cap, updated
-// rows per thread R (256 threads), map).
-#define LMS_MC_CONFIGS(MC)        \
-    MC(0, 128, 1024, 2, 16)       \
-    MC(1, 128, 1024, 2, 0)        \
-    MC(2, 256, 2048, 4, 16)       \
-    MC(3, 64, 512, 1, 16)
-constexpr int kNumMcConfigs = 4;
-
-struct MCShape {
-    int ts = 0, lcap = 0, r = 0, map = 0;
-};
-
-MCShape mc_shape(int cfg) {
-    switch (cfg) {
-#define MC(id, ts, lcap, r, map) \
-    case id:                     \
-        return MCShape{ts, lcap, r, map};
-        LMS_MC_CONFIGS(MC)
-#undef MC
-    }
-    return MCShape{};
-}
-
 const DeviceState::MCDev &ensure_mc(DeviceState &d, Mesh &M, const MCShape &t) {
     for (const auto &h : d.mcs)
         if (h.ts == t.ts && h.l_cap == t.lcap && h.u_cap == 256 * t.r) return h;
@@ -2642,6 +2667,7 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_CHECK(err);
+    if (M.n >= kDropPlansFrom) drop_unused_plans(d, M);
 }
 
 // The quality-fused form of a one-pass multicolour plan (false when some
