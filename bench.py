@@ -102,15 +102,14 @@ class Timer:
         self.ms = self.e0.elapsed_time(self.e1)
 
 
-def stream_copy_gbs(torch, mbytes=2048):
+def stream_copy_gbs(torch, mbytes=2048, reps=10):
     """Achieved bandwidth of a plain device copy (read + write bytes / time)."""
-    n = mbytes * (1 << 20) // 8
+    n = max(1, int(mbytes * (1 << 20)) // 8)
     a = torch.empty(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
     for _ in range(2):
         b.copy_(a)
-    reps = 10
     with Timer(torch) as t:
         for _ in range(reps):
             b.copy_(a)
@@ -144,9 +143,14 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
     ty = torch.empty_like(y)
     for _ in range(warmup):
         M.smooth(x, y, tx, ty, scheme=scheme, max_iters=sweeps, check_quality=False)
+    # one event after every step as well: per-step median and minimum, with no
+    # synchronisation inside the timed region
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     with Timer(torch) as t:
-        for _ in range(steps):
+        for i in range(steps):
             M.smooth(x, y, tx, ty, scheme=scheme, max_iters=sweeps, check_quality=False)
+            marks[i].record(t.s)
+    per_step = [t.e0.elapsed_time(marks[0])] + [marks[i - 1].elapsed_time(marks[i]) for i in range(1, steps)]
     info = M.info()
     s = 8 if prec == "f64" else 4
     b = sweep_bytes(info["n"], info["n_free"], info["nnz"], s)
@@ -155,6 +159,7 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
     out = dict(sweep_kernel=M.sweep_config(prec).split(" ")[0] if scheme == "jacobi" else "colour",
                vertex_updates_per_s=info["n_free"] * launches / t.wall,
                ms_per_step=t.wall * 1e3 / steps, sweep_us_events=sweep_us,
+               step_ms_median=float(np.median(per_step)), step_ms_min=float(min(per_step)),
                achieved_gbs=b / (sweep_us * 1e-6) / 1e9,
                frac_hbm=b / (sweep_us * 1e-6) / 1e9 / HBM_PEAK_GBS, bytes_per_sweep=b,
                wall=t.wall, ev_ms=t.ms)
@@ -162,7 +167,7 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
     return out, (x, y)
 
 
-def cpu_baseline(m, sweeps, budget_s=10.0):
+def cpu_baseline(m, sweeps, budget_s=10.0, one_core_s=3.0):
     from oracle import mesh as omesh
     from oracle import smooth as osm
     top = omesh.topology(m.n, m.tri)
@@ -178,9 +183,33 @@ def cpu_baseline(m, sweeps, budget_s=10.0):
         reps += 1
     wall = time.perf_counter() - w0
     free = int((top.fixed == 0).sum())
-    return dict(value=free * sweeps * reps / wall, unit="vertex-updates/s", cores=cores, kind="oracle",
-                sample=f"the full workload ({m.n} vertices, {sweeps} float64 Jacobi sweeps, ORI labels) "
-                       f"repeated {reps} times, OpenMP static schedule over {cores} threads"), top
+    out = dict(value=free * sweeps * reps / wall, unit="vertex-updates/s", cores=cores, kind="oracle",
+               sample=f"the full workload ({m.n} vertices, {sweeps} float64 Jacobi sweeps, ORI labels) "
+                      f"repeated {reps} times, OpenMP static schedule over {cores} threads",
+               host_cpu=host_cpu_model())
+    if one_core_s > 0:
+        # the same sweeps on one thread: runs of k1 sweeps (fewer than the
+        # workload's on a large mesh) repeated for about one_core_s seconds
+        k1 = max(1, min(sweeps, int(one_core_s * 1e8 / max(1, free))))
+        reps1 = 0
+        w0 = time.perf_counter()
+        while reps1 < 1 or time.perf_counter() - w0 < one_core_s:
+            osm.jacobi(top, m.x, m.y, k1, threads=1)
+            reps1 += 1
+        out["one_core_value"] = free * k1 * reps1 / (time.perf_counter() - w0)
+        out["one_core_sample"] = f"{k1} float64 Jacobi sweeps of the same mesh on one thread, {reps1} times"
+    return out, top
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def result_line(value, steps, warmup, ms_per_step, dtype, config, roofline, cpu, **extra):
@@ -208,6 +237,16 @@ def roofline_of(r, prec="f64", workload="ocean"):
             "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "sweep " + r["sweep_kernel"], "sweeps_per_launch": k,
             "bytes_per_launch": k * r["bytes_per_sweep"], "avg_launch_us": k * r["sweep_us_events"]}
+
+
+def with_stream_copy(torch, roof):
+    """Add the rate of a plain device copy that moves as many bytes (read +
+    write) as one launch of the dominant kernel, and the fraction of it the
+    kernel reaches: the practical ceiling at this size, beside the HBM peak."""
+    gbs = stream_copy_gbs(torch, mbytes=roof["bytes_per_launch"] / 2 / (1 << 20), reps=50)
+    roof["stream_copy_same_bytes_gbs"] = gbs
+    roof["frac_of_stream_copy"] = roof["achieved"] / gbs
+    return roof
 
 
 # ---------------------------------------------------------------- workloads
@@ -309,7 +348,7 @@ def bench_ocean(torch, args):
                      f"{SWEEPS} Jacobi sweeps per step, RDR ordering, float64",
          "n": info["n"], "n_free": info["n_free"], "n_tri": m.T, "nnz": info["nnz"],
          "sweeps_per_step": SWEEPS, "mesh_sha256": meshgen.mesh_hash(m)},
-        roofline_of(h, "f64", "ocean"), cpu, per_ordering=strip(results), extras=extras)
+        with_stream_copy(torch, roofline_of(h, "f64", "ocean")), cpu, per_ordering=strip(results), extras=extras)
 
 
 def strip(results):
@@ -382,7 +421,8 @@ def bench_graded16m(torch, args):
         {"workload": f"graded mesh refined 4x toward a seeded curve: {SWEEPS} Jacobi sweeps per step, "
                      "RDR ordering, float32 storage and accumulation",
          "n": info["n"], "n_free": info["n_free"], "n_tri": m.T, "nnz": info["nnz"], "sweeps_per_step": SWEEPS},
-        roofline_of(h, "f32", "graded16m"), cpu, per_ordering=strip(results), extras=extras)
+        with_stream_copy(torch, roofline_of(h, "f32", "graded16m")), cpu, per_ordering=strip(results),
+        extras=extras)
 
 
 def bench_batch512(torch, args):
@@ -404,20 +444,41 @@ def bench_batch512(torch, args):
             results[f"{kind}_{prec}"] = r
             log(f"{kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  sweep "
                 f"{r['sweep_us_events']:8.2f} us  {r['achieved_gbs']:8.1f} GB/s  [{r['sweep_kernel']}]")
+    # the same meshes split by size class, each class a batch of its own: the
+    # class that fits in LDS (<= 4096 vertices) runs all sweeps in one launch
+    # and may beat the per-sweep byte formula; the others run per sweep
+    by_size = {}
+    for label, lo, hi in (("n_le_4096", 0, 4096), ("n_4097_50000", 4097, 50000), ("n_gt_50000", 50001, 1 << 40)):
+        sub = [mm for mm in ms if lo <= mm.n <= hi]
+        if len(sub) < 2:
+            continue
+        cu, cv, ct = meshgen.concat(sub)
+        CB = lms.Mesh.build_csr_batched(cv, ct, np.concatenate([mm.tri for mm in sub]))
+        CB.reorder("rdr", x0=cu.x, y0=cu.y)
+        by_size[label] = dict(meshes=len(sub), n=cu.n)
+        for prec in ("f64", "f32"):
+            r, _ = run_fixed(torch, CB, cu, "rdr", prec, SWEEPS, args.steps, args.warmup)
+            by_size[label][prec] = dict(vertex_updates_per_s=r["vertex_updates_per_s"],
+                                        frac_of_hbm_by_sweep_formula=r["frac_hbm"], path=r["sweep_kernel"])
+            log(f"size class {label:13s} ({len(sub):3d} meshes, n={cu.n:9d}) {prec}: "
+                f"{r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  {r['frac_hbm']:.2f} of the HBM peak "
+                f"by the per-sweep bytes  [{r['sweep_kernel']}]")
+        del CB
+    extras = {"by_size_class_rdr": by_size}
     # a batch of small meshes (every one fits in LDS): all sweeps in one launch,
     # against the per-sweep path
     small = meshgen.batch(count=8192, seed=44, n_min=256, n_max=2000)
     su, sv, st_ = meshgen.concat(small)
     SB = lms.Mesh.build_csr_batched(sv, st_, np.concatenate([mm.tri for mm in small]))
     SB.reorder("rdr", x0=su.x, y0=su.y)
-    extras = {}
-    for flag, label in (("1", "one_launch"), ("0", "per_sweep")):
-        os.environ["LMS_SMALL_BATCH"] = flag
+    for flag, label in (("1", "one_launch"), ("0", "per_sweep"), (None, "tuned")):
+        if flag is not None:
+            os.environ["LMS_SMALL_BATCH"] = flag
         try:
             for prec in ("f64", "f32"):
                 r, _ = run_fixed(torch, SB, su, "rdr", prec, SWEEPS, args.steps, args.warmup)
                 extras[f"small_batch_{label}_{prec}"] = dict(vertex_updates_per_s=r["vertex_updates_per_s"],
-                                                             ms_per_step=r["ms_per_step"])
+                                                             ms_per_step=r["ms_per_step"], path=r["sweep_kernel"])
                 log(f"small batch ({len(small)} meshes, n={su.n}) {label:10s} {prec}: "
                     f"{r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s")
         finally:
@@ -428,7 +489,8 @@ def bench_batch512(torch, args):
         {"workload": f"batch of {len(ms)} jittered grids, sizes log-uniform 1k-200k vertices, "
                      f"{SWEEPS} sweeps each in one launch per sweep, RDR per mesh, float64",
          "n": info["n"], "n_mesh": len(ms), "sweeps_per_step": SWEEPS},
-        roofline_of(h, "f64", "batch512"), None, per_ordering=strip(results), extras=extras)
+        with_stream_copy(torch, roofline_of(h, "f64", "batch512")), None, per_ordering=strip(results),
+        extras=extras)
 
 
 def bench_graded64m(torch, args):
@@ -475,6 +537,19 @@ def bench_graded64m(torch, args):
             runs[name] = dict(iters=r["iters"], stopped_by=r["stopped_by"], q0=r["q0"],
                               q_final=r["q_final"], seconds_to_criterion=t.wall,
                               vertex_updates_per_s_incl_quality=info["n_free"] * r["iters"] / t.wall)
+            if fused == "1":
+                # sweep-only rate (as many fixed sweeps, no quality) and the
+                # cost of one quality pass, on the same state
+                k = max(1, r["iters"])
+                M.smooth(x, y, scheme=scheme, max_iters=2, check_quality=False)
+                with Timer(torch) as t:
+                    M.smooth(x, y, scheme=scheme, max_iters=k, check_quality=False)
+                runs[name]["vertex_updates_per_s_sweeps_only"] = info["n_free"] * k / t.wall
+                M.quality(x, y)
+                with Timer(torch) as t:
+                    for _ in range(5):
+                        M.quality(x, y)
+                runs[name]["quality_pass_us_incl_host_sync"] = t.wall * 1e6 / 5
             log(kind, name, runs[name])
         del x, y, x0, y0
     h = runs["rdr_jacobi"]

@@ -218,8 +218,12 @@ lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_p
  * ("" until the first lms_smooth or lms_sweep of that precision since the
  * last reorder).  The first sweep call per precision and ordering times every
  * variant on the caller's stream (synchronously) and keeps the fastest; all
- * variants give identical results.  buf: host char[len] out, NUL-terminated,
- * truncated to len-1 characters. */
+ * variants give identical results.  On a batched handle whose meshes all
+ * have at most 4096 vertices, the last fixed-K Jacobi call may have run every
+ * sweep in one launch (one workgroup per mesh); the name then starts with
+ * "small/r<rows per thread>/one-launch".  The first such call times that
+ * kernel against the tuned per-sweep path and keeps the faster.  buf: host
+ * char[len] out, NUL-terminated, truncated to len-1 characters. */
 lms_status lms_sweep_config(lms_mesh_t m, lms_precision p, char *buf, int32_t len);
 
 /* Free the handle and everything it owns.  NULL is accepted. */

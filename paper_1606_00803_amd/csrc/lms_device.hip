@@ -1459,6 +1459,9 @@ struct DeviceState {
     };
     std::deque<MCDev> mcs;       // uploaded one-pass multicolour plans of the current version
     int mc_cfg[2] = {-2, -2};    // one-pass multicolour variant per precision; -1 = colour by colour; -2 = not tuned
+    int small_cfg[2] = {-2, -2}; // batch of small meshes: 1 = all sweeps in one launch, 0 = per sweep; -2 = not decided
+    float small_us[2] = {-1.f, -1.f};  // measured one-launch time per sweep (microseconds)
+    bool small_used[2] = {false, false};  // the last fixed-K Jacobi call ran the one-launch path
     int32_t *ta = nullptr, *tb = nullptr, *tc = nullptr, *vt_ptr = nullptr, *vt = nullptr;
     double *tw = nullptr;
     int32_t *trec = nullptr;
@@ -1582,6 +1585,9 @@ DeviceState &ensure_device(Mesh &M) {
         d->tbs.clear();
         d->mcs.clear();
         d->mc_cfg[0] = d->mc_cfg[1] = -2;
+        d->small_cfg[0] = d->small_cfg[1] = -2;
+        d->small_us[0] = d->small_us[1] = -1.f;
+        d->small_used[0] = d->small_used[1] = false;
         d->version = ~uint64_t(0);
         d->row_ptr = upload(d, M.row_ptr);
         d->col = upload(d, M.col);
@@ -2486,6 +2492,56 @@ void launch_small_meshes(DeviceState &d, const Mesh &M, vec2_t<T> *A, vec2_t<T> 
     launch_check();
 }
 
+// Whether a batch of small meshes runs all its sweeps in one launch (one
+// workgroup per mesh) or one launch per sweep.  The one-launch kernel wins
+// with many meshes; with few, its workgroups leave most of the chip idle and
+// the per-sweep path, tuned first, is faster.  So time the one-launch kernel
+// over a few sweeps and keep it if its time per sweep beats the per-sweep
+// path's tuned one.  LMS_SMALL_BATCH=1 forces the one-launch path, 0 turns it
+// off.  Returns the rows per thread of the one-launch kernel, or 0.
+template <typename T>
+int choose_small_batch(DeviceState &d, Mesh &M, T *x, T *y, T *tx, T *ty, hipStream_t s) {
+    const int rows = small_batch_rows(M);
+    const int pi = sizeof(T) == 8 ? 0 : 1;
+    if (rows == 0) return 0;
+    if (const char *f = std::getenv("LMS_SMALL_BATCH"); f && *f) return rows;  // forced on (0 gave rows == 0)
+    if (d.small_cfg[pi] == -2) {
+        tune_sweep<T>(d, M, x, y, tx, ty, s);
+        float per_sweep = 3.0e38f;
+        for (int c : {d.tb_cfg[pi], d.smooth_cfg[pi]})
+            if (c >= 0 && d.tune_us[pi][c] >= 0.f) per_sweep = std::min(per_sweep, d.tune_us[pi][c]);
+        vec2_t<T> *A = ensure_packed<T>(d, 0, M.n);
+        vec2_t<T> *B = ensure_packed<T>(d, 1, M.n);
+        k_pack<T><<<(M.n + 255) / 256, 256, 0, s>>>(x, y, A, B, M.n);
+        launch_check();
+        constexpr int32_t kK = 8, kReps = 3;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_CHECK(hipEventCreate(&e0));
+        hipError_t err = hipEventCreate(&e1);
+        if (err != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            HIP_CHECK(err);
+        }
+        launch_small_meshes<T>(d, M, A, B, 2, rows, s);
+        err = hipEventRecord(e0, s);
+        for (int r = 0; r < kReps && err == hipSuccess; ++r) launch_small_meshes<T>(d, M, A, B, kK, rows, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIP_CHECK(err);
+        d.small_us[pi] = ms * 1000.f / float(kK * kReps);
+        d.small_cfg[pi] = d.small_us[pi] < per_sweep ? 1 : 0;
+        if (env_flag("LMS_VERBOSE", false))
+            std::fprintf(stderr, "[lms] small-mesh batch (%s, %d meshes): one launch %.2f us per sweep, per sweep %.2f us: %s\n",
+                         pi == 0 ? "f64" : "f32", M.n_mesh, double(d.small_us[pi]), double(per_sweep),
+                         d.small_cfg[pi] == 1 ? "one launch" : "per sweep");
+    }
+    return d.small_cfg[pi] == 1 ? rows : 0;
+}
+
 // Runs the stopping rule's chunks and returns the final device state.  One
 // chunk stays queued ahead of the host's check: chunk i+1 is issued before
 // the state after chunk i is read back.  The stop flag never goes down and
@@ -2701,7 +2757,7 @@ bool ensure_mcq(DeviceState &d, Mesh &M, const MCShape &t) {
 // sweep back and forth between them (graph-captured), unpack the last one.
 template <typename T>
 void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_scheme sch, const lms_smooth_opts &o,
-                   hipStream_t s, lms_smooth_result &r) {
+                   hipStream_t s, lms_smooth_result &r, int small = 0) {
     const int pi = sizeof(T) == 8 ? 0 : 1;
     const bool colour = sch == LMS_MULTICOLOR;
     const int cfg = colour ? -1 : d.smooth_cfg[pi];
@@ -2728,7 +2784,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     };
     int32_t iters = 0;
     bool in_b = false;  // the result sits in B
-    const int small_rows = colour || o.check_quality ? 0 : small_batch_rows(M);
+    const int small_rows = colour || o.check_quality ? 0 : small;
     if (small_rows > 0) {
         // every mesh of the batch fits in LDS: all K sweeps in one launch
         const int32_t K = o.max_iters;
@@ -2871,12 +2927,16 @@ template <typename T>
 void smooth_typed(Mesh &M, DeviceState &d, T *x, T *y, T *tx, T *ty, lms_precision p, lms_scheme sch,
                   const lms_smooth_opts &o, hipStream_t s, lms_smooth_result &r) {
     if (sch == LMS_JACOBI) {
-        if (!o.check_quality && small_batch_rows(M) > 0) {
-            smooth_packed<T>(M, d, x, y, p, sch, o, s, r);
+        const int pi = sizeof(T) == 8 ? 0 : 1;
+        const int small = !o.check_quality && small_batch_rows(M) > 0
+                              ? choose_small_batch<T>(d, M, x, y, tx, ty, s)
+                              : 0;
+        if (!o.check_quality) d.small_used[pi] = small > 0;
+        if (small > 0) {
+            smooth_packed<T>(M, d, x, y, p, sch, o, s, r, small);
             return;
         }
         tune_sweep<T>(d, M, x, y, tx, ty, s);
-        const int pi = sizeof(T) == 8 ? 0 : 1;
         if (sweep_config_packed(d.smooth_cfg[pi]) || (!o.check_quality && d.tb_cfg[pi] >= 0) ||
             (o.check_quality && fused_stop_cfg<T>(d, M) >= 0)) {
             smooth_packed<T>(M, d, x, y, p, sch, o, s, r);
@@ -3068,11 +3128,15 @@ std::string dev_sweep_config(Mesh &M, lms_precision p) {
     if (!M.dev || M.dev->version != M.version) return "";
     const int pi = p == LMS_FP64 ? 0 : 1;
     const int c = M.dev->smooth_cfg[pi];
-    if (c < 0) return "";
-    // first the variant a fixed-K Jacobi lms_smooth runs, then the one it
-    // runs under the stopping rule
+    // a batch of small meshes that runs all sweeps in one launch names that first
+    std::string small;
+    if (M.dev->small_used[pi]) small = "small/r" + std::to_string(small_batch_rows(M)) + "/one-launch";
+    if (c < 0) return small;
+    // then the variant a fixed-K Jacobi lms_smooth runs, then the one it runs
+    // under the stopping rule
     std::string out = M.dev->tb_cfg[pi] >= 0 ? sweep_config_name(M.dev->tb_cfg[pi]) + " " + sweep_config_name(c)
                                              : sweep_config_name(c);
+    if (!small.empty()) out = small + " " + out;
     char buf[64];
     for (int i = 0; i < kNumAllConfigs; ++i) {
         std::snprintf(buf, sizeof(buf), "%s%d:%.2fus", i == 0 ? " tuned[" : " ", i,

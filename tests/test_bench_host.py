@@ -1,0 +1,72 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the byte model, the
+sweeps-per-launch parse, the counter-summary lookup and the oracle baseline's
+report fields."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import meshgen  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def test_sweep_bytes_counts_each_stream_once():
+    # x and y of every vertex read (2*s*n), of every free vertex written
+    # (2*s*n_free), 4*(n+1) row offsets, 4*nnz column ids
+    assert bench.sweep_bytes(10, 7, 30, 8) == 2 * 8 * 10 + 2 * 8 * 7 + 4 * 11 + 4 * 30
+    assert bench.sweep_bytes(10, 7, 30, 4) == 2 * 4 * 10 + 2 * 4 * 7 + 4 * 11 + 4 * 30
+
+
+def test_sweeps_per_launch_reads_the_blocking_depth():
+    assert bench.sweeps_per_launch("tb/ts256/k2/bs256/w8/r2/l1024/xcd16") == 2
+    assert bench.sweeps_per_launch("tb/ts512/k4/bs512/w8/r8/l4096/linear") == 4
+    assert bench.sweeps_per_launch("halo/ts256/w8/xcd") == 1
+    assert bench.sweeps_per_launch("ell2/bs128/w8/r2/linear") == 1
+
+
+def test_roofline_scales_bytes_and_time_by_the_depth():
+    r = dict(sweep_kernel="tb/ts256/k2/bs256/w8/r2/l1024/xcd16", achieved_gbs=4000.0,
+             bytes_per_sweep=1000, sweep_us_events=3.0)
+    roof = bench.roofline_of(r, "f64", "no-such-workload")
+    assert roof["bytes_per_launch"] == 2000 and roof["avg_launch_us"] == 6.0
+    assert roof["frac"] == pytest.approx(0.5) and roof["traffic"] is None and roof["bound"] == "hbm"
+
+
+def test_counter_summary_is_used_only_for_the_current_source(tmp_path):
+    row = "| `tb/ts256/k2/bs256/w8/r2/l1024/xcd16` | f64 | 1.0 / 2.0 | 84461085 | 1.014 |  |\n"
+    good = tmp_path / "good.md"
+    good.write_text(f"- source_sha256: {bench.device_source_hash()}\n\n" + row)
+    stale = tmp_path / "stale.md"
+    stale.write_text("- source_sha256: " + "0" * 64 + "\n\n" + row)
+    name = "tb/ts256/k2/bs256/w8/r2/l1024/xcd16"
+    assert bench.counters_traffic(name, "f64", str(good)) == 84461085.0
+    assert bench.counters_traffic(name, "f32", str(good)) is None
+    assert bench.counters_traffic("halo/ts256/w8/xcd", "f64", str(good)) is None
+    assert bench.counters_traffic(name, "f64", str(stale)) is None
+    assert bench.counters_traffic(name, "f64", str(tmp_path / "missing.md")) is None
+
+
+def test_oracle_baseline_reports_its_sample():
+    m = meshgen.jittered_grid(40, seed=1)
+    cpu, top = bench.cpu_baseline(m, 3, budget_s=0.0, one_core_s=0.05)
+    free = int((top.fixed == 0).sum())
+    assert cpu["kind"] == "oracle" and cpu["unit"] == "vertex-updates/s"
+    assert 1 <= cpu["cores"] <= 16 and cpu["value"] > 0 and cpu["one_core_value"] > 0
+    assert f"{m.n} vertices" in cpu["sample"] and free > 0
+    assert "one thread" in cpu["one_core_sample"]
+    assert np.isfinite(cpu["value"])

@@ -467,16 +467,23 @@ def test_small_mesh_batch_in_one_launch(prec, K, sizes):
     u, v_off, t_off = meshgen.concat(ms)
     local = np.concatenate([m.tri for m in ms])
     outs = []
-    for flag in ("1", "0"):
-        os.environ["LMS_SMALL_BATCH"] = flag
+    for flag in ("1", "0", None):                    # forced, off, chosen by timing both
+        if flag is not None:
+            os.environ["LMS_SMALL_BATCH"] = flag
         try:
             B = lms.Mesh.build_csr_batched(v_off, t_off, local)
             x, y, r, _ = run_library(u, "rdr", K, dtype=dt, M=B)
         finally:
             os.environ.pop("LMS_SMALL_BATCH", None)
         assert r["iters"] == K
+        name = B.sweep_config(prec)
+        if flag == "1":
+            assert name.startswith("small/r"), name
+        elif flag == "0":
+            assert not name.startswith("small/"), name
         outs.append((x, y))
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1])
     if prec == "f64":
         for i in (0, 7, count // 2, count - 1):
             m = ms[i]
