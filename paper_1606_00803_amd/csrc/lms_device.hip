@@ -617,6 +617,10 @@ __device__ __forceinline__ double block_sum(double v, double *s_red);
 // size), KP (the plan's depth) and LCAP (its staging cap) name the variant
 // whose plan the kernel reads; the tiles themselves come from tile_ptr.
 //
+// G (patch tiles): the tile's own rows are not a range but the first nown
+// entries of its staged-row list (halo_ptr/halo then cover every staged row),
+// read and written through it.
+//
 // QUAL (the stopping rule, Section 5.1): the pass also evaluates the quality
 // (Section 3.2) of each state it starts a sweep from.  Before sweep j+1 the
 // own rows and ring 1 hold state s+j, and every triangle of the tile (those
@@ -624,7 +628,7 @@ __device__ __forceinline__ double block_sum(double v, double *s_red);
 // tile's sum of w_t q_t goes to qpart[j*gridDim.x + tile].  The depth comes
 // from the device state: k = min(KP, max_iters - swept), and a pass of depth
 // 0 (all sweeps done) evaluates its source state only.
-template <typename T, int BS, int W, int R, int MAP, int TS, int KP, int LCAP, bool QUAL>
+template <typename T, int BS, int W, int R, int MAP, int TS, int KP, int LCAP, bool QUAL, bool G>
 __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ tile_ptr,
                                                   const int32_t *__restrict__ ring, int32_t k,
                                                   const int64_t *__restrict__ halo_ptr,
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     }
     const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
     const int tid = int(threadIdx.x);
-    const int32_t b = tile_ptr[tile];
+    const int32_t b = G ? 0 : tile_ptr[tile];
     static_assert(KP >= 1 && KP <= 8 && TS > 0 && LCAP > 0, "plan shape");
     const int32_t *rc = ring + int64_t(tile) * (KP + 1);
     const int32_t nown = rc[0], nload = rc[k > 0 ? k : 1], nupd = k > 0 ? rc[k - 1] : 0;
@@ -681,8 +685,10 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             for (int q = 0; q < W / 2; ++q) wd[r][q] = 0xFFFFFFFFu;
         }
     }
-    for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
-    const int32_t nh = nload - nown;
+    if constexpr (!G)
+        for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
+    const int32_t g0 = G ? 0 : nown;  // first staged row read through the list
+    const int32_t nh = nload - g0;
     for (int32_t j0 = tid; j0 < nh; j0 += 4 * BS) {
         int32_t g[4];
 #pragma unroll
@@ -704,7 +710,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
                 vec2_t<T> h;
                 h.x = hx[q];
                 h.y = hy[q];
-                sp[nown + j0 + q * BS] = h;
+                sp[g0 + j0 + q * BS] = h;
             }
     }
     __syncthreads();
@@ -765,7 +771,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
         if (j == k) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (w[r]) dst[b + tid + BS * r] = o[r];
+                if (w[r]) dst[G ? halo[hb + tid + BS * r] : b + tid + BS * r] = o[r];
         } else {
             __syncthreads();
 #pragma unroll
@@ -1427,6 +1433,7 @@ struct DeviceState {
     std::deque<HaloDev> halos;   // uploaded tile plans of the current version (stable references)
     struct TBDev {
         int32_t ts = 0, k = 0, u_cap = 0, l_cap = 0, tiles = 0, l_max = 0, u_max = 0;
+        bool patches = false;
         bool fits = false;
         int32_t *tile_ptr = nullptr, *ring = nullptr, *halo = nullptr;
         int64_t *halo_ptr = nullptr, *lidx_ptr = nullptr;
@@ -1494,7 +1501,7 @@ struct DeviceState {
     bool last_valid = false;
     void *pk[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [precision][ping|pong] interleaved copies
     size_t pk_n[2] = {0, 0};
-    float tune_us[2][64] = {};       // measured time per variant (microseconds per sweep)
+    float tune_us[2][80] = {};       // measured time per variant (microseconds per sweep)
 };
 
 namespace {
@@ -1691,47 +1698,56 @@ constexpr int kNumSweepConfigs = 44;
 constexpr int kDefaultSweepConfig = 0;
 
 // Temporally blocked variants, k sweeps per pass over memory:
-// TB(id, block size, padded width, rows per thread, MAP, tile size, k).
 // TB(id, block size, padded width, rows per thread, MAP, nominal tile size,
-//    k, staging cap in rows).  A tile whose first sweep would update more
-// than block size x rows per thread rows, or whose staging area would pass
-// the cap, is halved until it fits.
-#define LMS_TB_CONFIGS(TB)                 \
-    TB(44, 128, 8, 2, 0, 128, 2, 512)      \
-    TB(45, 256, 8, 2, 0, 256, 2, 1024)     \
-    TB(46, 256, 8, 2, -1, 256, 2, 1024)    \
-    TB(47, 256, 8, 2, 16, 256, 2, 1024)    \
-    TB(48, 256, 8, 4, 0, 256, 2, 2048)     \
-    TB(49, 256, 8, 4, 0, 512, 2, 2048)     \
-    TB(50, 256, 8, 4, -1, 512, 2, 2048)    \
-    TB(51, 256, 8, 4, 0, 256, 3, 2048)     \
-    TB(52, 256, 8, 8, 0, 512, 3, 4096)     \
-    TB(53, 256, 8, 8, 0, 1024, 2, 4096)    \
-    TB(54, 512, 8, 8, 0, 512, 4, 4096)     \
-    TB(55, 128, 8, 2, 16, 128, 2, 512)     \
-    TB(56, 256, 12, 4, 0, 512, 2, 2048)    \
-    TB(57, 256, 12, 4, -1, 512, 2, 2048)   \
-    TB(58, 256, 12, 8, 0, 1024, 2, 4096)   \
-    TB(59, 256, 12, 4, 0, 256, 3, 2048)    \
-    TB(60, 256, 12, 2, 0, 256, 2, 1024)    \
-    TB(61, 256, 16, 4, 0, 512, 2, 2048)    \
-    TB(62, 256, 16, 2, 0, 256, 2, 1024)    \
-    TB(63, 256, 16, 4, -1, 512, 2, 2048)
+//    k, staging cap in rows, patches).  A tile whose first sweep would update
+// more than block size x rows per thread rows, or whose staging area would
+// pass the cap, is halved until it fits.  patches = 0: a tile is a range of
+// consecutive rows; 1: a compact patch of free rows grown breadth-first over
+// the adjacency, its rows read and written through the staged-row list.  A
+// range of an ordering whose walk restarts (RDR's) or that runs in long
+// strips (ORI's) is spread out in the mesh and stages about 2.9 rows per own
+// row at depth 2; a patch stages about 1.7.
+#define LMS_TB_CONFIGS(TB)                   \
+    TB(44, 128, 8, 2, 0, 128, 2, 512, 0)     \
+    TB(45, 256, 8, 2, 0, 256, 2, 1024, 0)    \
+    TB(46, 256, 8, 2, -1, 256, 2, 1024, 0)   \
+    TB(47, 256, 8, 2, 16, 256, 2, 1024, 0)   \
+    TB(48, 256, 8, 4, 0, 256, 2, 2048, 0)    \
+    TB(49, 256, 8, 4, 0, 512, 2, 2048, 0)    \
+    TB(50, 256, 8, 4, -1, 512, 2, 2048, 0)   \
+    TB(51, 256, 8, 4, 0, 256, 3, 2048, 0)    \
+    TB(52, 256, 8, 8, 0, 512, 3, 4096, 0)    \
+    TB(53, 256, 8, 8, 0, 1024, 2, 4096, 0)   \
+    TB(54, 512, 8, 8, 0, 512, 4, 4096, 0)    \
+    TB(55, 128, 8, 2, 16, 128, 2, 512, 0)    \
+    TB(56, 256, 12, 4, 0, 512, 2, 2048, 0)   \
+    TB(57, 256, 12, 4, -1, 512, 2, 2048, 0)  \
+    TB(58, 256, 12, 8, 0, 1024, 2, 4096, 0)  \
+    TB(59, 256, 12, 4, 0, 256, 3, 2048, 0)   \
+    TB(60, 256, 12, 2, 0, 256, 2, 1024, 0)   \
+    TB(61, 256, 16, 4, 0, 512, 2, 2048, 0)   \
+    TB(62, 256, 16, 2, 0, 256, 2, 1024, 0)   \
+    TB(63, 256, 16, 4, -1, 512, 2, 2048, 0)  \
+    TB(64, 256, 8, 2, 16, 256, 2, 1024, 1)   \
+    TB(65, 256, 8, 4, 0, 512, 2, 2048, 1)    \
+    TB(66, 256, 8, 4, 16, 256, 3, 1024, 1)   \
+    TB(67, 256, 8, 8, 0, 512, 4, 2048, 1)    \
+    TB(68, 512, 8, 4, 0, 512, 4, 2048, 1)
 constexpr int kFirstTBConfig = kNumSweepConfigs;
-constexpr int kNumAllConfigs = 64;
-static_assert(kNumAllConfigs <= 64, "tune_us holds 64 variants");
+constexpr int kNumAllConfigs = 69;
+static_assert(kNumAllConfigs <= 80, "tune_us holds 80 variants");
 
 struct TBShape {
-    int bs = 0, w = 0, r = 0, map = 0, ts = 0, k = 0, lcap = 0;
+    int bs = 0, w = 0, r = 0, map = 0, ts = 0, k = 0, lcap = 0, g = 0;  // g: tiles are patches
 };
 
 bool is_tb_config(int cfg) { return cfg >= kFirstTBConfig && cfg < kNumAllConfigs; }
 
 TBShape tb_shape(int cfg) {
     switch (cfg) {
-#define TB(id, bs, w, r, map, ts, k, lcap) \
-    case id:                               \
-        return TBShape{bs, w, r, map, ts, k, lcap};
+#define TB(id, bs, w, r, map, ts, k, lcap, g) \
+    case id:                                  \
+        return TBShape{bs, w, r, map, ts, k, lcap, g};
         LMS_TB_CONFIGS(TB)
 #undef TB
     }
@@ -1749,8 +1765,8 @@ std::string sweep_config_name(int cfg) {
     char buf[96];
     if (is_tb_config(cfg)) {
         const TBShape t = tb_shape(cfg);
-        std::snprintf(buf, sizeof(buf), "tb/ts%d/k%d/bs%d/w%d/r%d/l%d/%s", t.ts, t.k, t.bs, t.w, t.r, t.lcap,
-                      map_name(t.map).c_str());
+        std::snprintf(buf, sizeof(buf), "tb/ts%d/k%d/bs%d/w%d/r%d/l%d/%s%s", t.ts, t.k, t.bs, t.w, t.r, t.lcap,
+                      map_name(t.map).c_str(), t.g ? "/patch" : "");
         return buf;
     }
     switch (cfg) {
@@ -1907,17 +1923,19 @@ const DeviceState::HaloDev &ensure_halo(DeviceState &d, Mesh &M, int32_t ts) {
 
 const DeviceState::TBDev *find_tb(const DeviceState &d, const TBShape &t) {
     for (const auto &h : d.tbs)
-        if (h.ts == t.ts && h.k == t.k && h.u_cap == t.bs * t.r && h.l_cap == t.lcap) return &h;
+        if (h.ts == t.ts && h.k == t.k && h.u_cap == t.bs * t.r && h.l_cap == t.lcap && h.patches == (t.g != 0))
+            return &h;
     return nullptr;
 }
 
 // Build (host) and upload the temporal-blocking plan of variant shape t.
 const DeviceState::TBDev &ensure_tb(DeviceState &d, Mesh &M, const TBShape &t) {
     if (const DeviceState::TBDev *h = find_tb(d, t)) return *h;
-    const Mesh::TBPlan &P = tb_plan(M, t.ts, t.k, t.bs * t.r, t.lcap);
+    const Mesh::TBPlan &P = tb_plan(M, t.ts, t.k, t.bs * t.r, t.lcap, t.g != 0);
     DeviceState::TBDev h;
     h.ts = t.ts;
     h.k = t.k;
+    h.patches = t.g != 0;
     h.u_cap = t.bs * t.r;
     h.l_cap = t.lcap;
     h.fits = P.fits;
@@ -1942,7 +1960,9 @@ bool ensure_tbq(DeviceState &d, Mesh &M, const TBShape &t) {
     if (h->q_ready) return h->q_fits;
     Mesh::TBPlan *P = nullptr;
     for (auto &p : M.tb_plans)
-        if (p.ts == t.ts && p.k == t.k && p.u_cap == t.bs * t.r && p.l_cap == t.lcap && p.version == M.version) P = &p;
+        if (p.ts == t.ts && p.k == t.k && p.u_cap == t.bs * t.r && p.l_cap == t.lcap && p.patches == (t.g != 0) &&
+            p.version == M.version)
+            P = &p;
     if (!P) fail(LMS_ERR_STATE, "tile plan missing on the host");
     tb_quality_plan(M, *P);
     h->q_ready = true;
@@ -2032,14 +2052,14 @@ void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T>
     if (h->tiles == 0) return;
     const size_t lds = size_t(h->l_max) * sizeof(vec2_t<T>);
     switch (cfg) {
-#define TB(id, bs, w, r, map, ts, kk, lcap)                                                                    \
+#define TB(id, bs, w, r, map, ts, kk, lcap, g)                                                                 \
     case id:                                                                                                   \
         if (qual)                                                                                              \
-            k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, true><<<h->tiles, bs, lds, s>>>(                       \
+            k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, true, g != 0><<<h->tiles, bs, lds, s>>>(               \
                 h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, h->qtri_ptr,     \
                 h->qtri, h->qpart, d.st, max_iters);                                                           \
         else                                                                                                   \
-            k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, false><<<h->tiles, bs, lds, s>>>(                      \
+            k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, false, g != 0><<<h->tiles, bs, lds, s>>>(              \
                 h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, nullptr,        \
                 nullptr, nullptr, nullptr, 0);                                                                 \
         break;
@@ -2156,11 +2176,12 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
             if (!is_tb_config(c) && sweep_config_tile(c) == ts) return true;
         return false;
     };
-    auto keep_tb = [&](int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap) {
+    auto keep_tb = [&](int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap, bool patches) {
         for (int c : keep)
             if (is_tb_config(c)) {
                 const TBShape t = tb_shape(c);
-                if (t.ts == ts && t.k == k && t.bs * t.r == u_cap && t.lcap == l_cap) return true;
+                if (t.ts == ts && t.k == k && t.bs * t.r == u_cap && t.lcap == l_cap && (t.g != 0) == patches)
+                    return true;
             }
         return false;
     };
@@ -2176,7 +2197,7 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
         it = d.halos.erase(it);
     }
     for (auto it = d.tbs.begin(); it != d.tbs.end();) {
-        if (keep_tb(it->ts, it->k, it->u_cap, it->l_cap)) {
+        if (keep_tb(it->ts, it->k, it->u_cap, it->l_cap, it->patches)) {
             ++it;
             continue;
         }
@@ -2217,7 +2238,7 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
     for (auto it = M.halo_plans.begin(); it != M.halo_plans.end();)
         it = keep_ts(it->ts) ? std::next(it) : M.halo_plans.erase(it);
     for (auto it = M.tb_plans.begin(); it != M.tb_plans.end();)
-        it = keep_tb(it->ts, it->k, it->u_cap, it->l_cap) ? std::next(it) : M.tb_plans.erase(it);
+        it = keep_tb(it->ts, it->k, it->u_cap, it->l_cap, it->patches) ? std::next(it) : M.tb_plans.erase(it);
 }
 
 // Autotuner: time every sweep variant on this mesh (src -> dst, which leaves

@@ -679,33 +679,69 @@ struct TBPart {
 
 }  // namespace
 
-const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap) {
+const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap, bool patches) {
     for (const auto &h : M.tb_plans)
-        if (h.ts == ts && h.k == k && h.u_cap == u_cap && h.l_cap == l_cap && h.version == M.version) return h;
+        if (h.ts == ts && h.k == k && h.u_cap == u_cap && h.l_cap == l_cap && h.patches == patches &&
+            h.version == M.version)
+            return h;
     if (M.ell_w <= 0) fail(LMS_ERR_STATE, "no padded adjacency for a temporal-blocking plan");
     if (ts <= 0 || k < 1 || k > 8 || u_cap < 1 || l_cap < u_cap || l_cap >= 0xFFFF)
         fail(LMS_ERR_ARG, "temporal-blocking plan: bad tile size, depth or caps");
     const int32_t n = M.n, W = M.ell_w;
     const int64_t nominal = (int64_t(n) + ts - 1) / ts;
-    const int workers = host_threads(nominal);
+    // Patches: seeds in ascending label order; from each free row not yet
+    // taken, take up to ts free rows not yet taken, in breadth-first order
+    // over the adjacency (one pass over the mesh; a patch may reach rows of
+    // any label, which gathers the scattered end of an ordering into the
+    // patches around it).  patch_rows lists each patch in that order.
+    std::vector<int64_t> patch_ptr(1, 0);
+    std::vector<int32_t> patch_rows;
+    if (patches) {
+        std::vector<uint8_t> taken(size_t(n), 0);
+        resize_or_fail(patch_rows, size_t(M.n_free));
+        patch_rows.clear();
+        std::vector<int32_t> grow;
+        for (int32_t seed = 0; seed < n; ++seed) {
+            if (M.fixed[size_t(seed)] || taken[size_t(seed)]) continue;
+            grow.assign(1, seed);
+            taken[size_t(seed)] = 1;
+            for (size_t h = 0; h < grow.size() && h < size_t(ts); ++h) {
+                const int32_t v = grow[h];
+                for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                    const int32_t u = M.col[size_t(j)];
+                    if (!M.fixed[size_t(u)] && !taken[size_t(u)]) {
+                        taken[size_t(u)] = 1;
+                        grow.push_back(u);
+                    }
+                }
+            }
+            for (size_t i = size_t(ts); i < grow.size(); ++i) taken[size_t(grow[i])] = 0;  // give the rest back
+            grow.resize(std::min(grow.size(), size_t(ts)));
+            patch_rows.insert(patch_rows.end(), grow.begin(), grow.end());
+            patch_ptr.push_back(int64_t(patch_rows.size()));
+        }
+    }
+    const int64_t items = patches ? int64_t(patch_ptr.size()) - 1 : nominal;
+    const int workers = host_threads(items);
     std::vector<TBPart> parts(static_cast<size_t>(workers));
     std::atomic<bool> give_up{false};
     std::atomic<int64_t> all_own{0}, all_staged{0};
     const int64_t sample = std::max<int64_t>(4096, int64_t(n) / 16);
-    parallel_runs(nominal, workers, [&](int w, int64_t first, int64_t last) {
+    parallel_runs(items, workers, [&](int w, int64_t first, int64_t last) {
         TBPart &out = parts[size_t(w)];
         SlotMap slots(size_t(l_cap) + size_t(W) + 1);
         std::vector<int32_t> local;
         int32_t rc[9];
-        // Stage rows [b, e) and k rings; false as soon as a cap is exceeded.
-        auto try_tile = [&](int32_t b, int32_t e) {
+        // Stage the own rows (ascending) and k rings; false as soon as a cap
+        // is exceeded.
+        auto try_tile = [&](const int32_t *own, int32_t nown) {
             slots.clear();
             local.clear();
-            for (int32_t v = b; v < e; ++v) {
-                slots.insert(v, v - b);
-                local.push_back(v);
+            for (int32_t i = 0; i < nown; ++i) {
+                slots.insert(own[i], i);
+                local.push_back(own[i]);
             }
-            rc[0] = e - b;
+            rc[0] = nown;
             if (rc[0] > l_cap) return false;
             size_t from = 0;  // first local row of the ring being expanded
             for (int32_t m = 1; m <= k; ++m) {
@@ -725,13 +761,14 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
             }
             return rc[k - 1] <= u_cap;
         };
-        auto emit_tile = [&](int32_t b, int32_t e) {
-            out.tile_end.push_back(e);
+        auto emit_tile = [&]() {
+            const int32_t nown = rc[0];
+            out.tile_end.push_back(patches ? nown : local[size_t(nown) - 1] + 1);
             out.ring.insert(out.ring.end(), rc, rc + k + 1);
             out.l_max = std::max(out.l_max, rc[k]);
             out.u_max = std::max(out.u_max, rc[k - 1]);
-            out.halo.insert(out.halo.end(), local.begin() + (e - b), local.end());
-            out.halo_n.push_back(rc[k] - rc[0]);
+            out.halo.insert(out.halo.end(), local.begin() + (patches ? 0 : nown), local.end());
+            out.halo_n.push_back(patches ? rc[k] : rc[k] - rc[0]);
             const size_t rows = size_t(rc[k - 1]);
             const size_t base = out.lidx.size();
             out.lidx.resize(base + rows * size_t(W), uint16_t(0xFFFF));
@@ -746,33 +783,77 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
             }
             out.lidx_rows.push_back(int32_t(rows));
         };
-        std::vector<std::pair<int32_t, int32_t>> todo;
-        for (int64_t t = first; t < last && out.fits; ++t) {
-            if (give_up.load(std::memory_order_relaxed)) {
+        // count the tile; false (and give up everywhere) once the staged rows
+        // per own row exceed the limit
+        auto account = [&]() {
+            const int64_t own = all_own.fetch_add(rc[0]) + rc[0];
+            const int64_t staged = all_staged.fetch_add(rc[k]) + rc[k];
+            if (own > sample && staged > kTBMaxStagedPerRow * own) {
                 out.fits = false;
-                break;
+                give_up.store(true, std::memory_order_relaxed);
+                return false;
             }
-            todo.emplace_back(int32_t(t * ts), int32_t(std::min<int64_t>(n, (t + 1) * ts)));
-            while (!todo.empty()) {
-                const auto [b, e] = todo.back();
-                todo.pop_back();
-                if (try_tile(b, e)) {
-                    emit_tile(b, e);
-                    const int64_t own = all_own.fetch_add(rc[0]) + rc[0];
-                    const int64_t staged = all_staged.fetch_add(rc[k]) + rc[k];
-                    if (own > sample && staged > kTBMaxStagedPerRow * own) {
-                        out.fits = false;
-                        give_up.store(true, std::memory_order_relaxed);
+            return true;
+        };
+        auto fail_here = [&]() {
+            out.fits = false;
+            give_up.store(true, std::memory_order_relaxed);
+        };
+        if (!patches) {
+            std::vector<std::pair<int32_t, int32_t>> todo;
+            std::vector<int32_t> own;
+            for (int64_t t = first; t < last && out.fits; ++t) {
+                if (give_up.load(std::memory_order_relaxed)) {
+                    out.fits = false;
+                    break;
+                }
+                todo.emplace_back(int32_t(t * ts), int32_t(std::min<int64_t>(n, (t + 1) * ts)));
+                while (!todo.empty()) {
+                    const auto [b, e] = todo.back();
+                    todo.pop_back();
+                    own.resize(size_t(e - b));
+                    for (int32_t v = b; v < e; ++v) own[size_t(v - b)] = v;
+                    if (try_tile(own.data(), e - b)) {
+                        emit_tile();
+                        if (!account()) break;
+                    } else if (e - b > 1) {  // halve; the left half goes first
+                        const int32_t mid = b + (e - b) / 2;
+                        todo.emplace_back(mid, e);
+                        todo.emplace_back(b, mid);
+                    } else {
+                        fail_here();
                         break;
                     }
-                } else if (e - b > 1) {  // halve; the left half goes first
-                    const int32_t mid = b + (e - b) / 2;
-                    todo.emplace_back(mid, e);
-                    todo.emplace_back(b, mid);
-                } else {
+                }
+            }
+        } else {
+            // each patch; while a cap is exceeded, split it into the first
+            // and second half of its breadth-first order (the first half is a
+            // smaller ball around the seed), first half first
+            std::vector<std::pair<int64_t, int64_t>> todo;
+            std::vector<int32_t> own;
+            for (int64_t t = first; t < last && out.fits; ++t) {
+                if (give_up.load(std::memory_order_relaxed)) {
                     out.fits = false;
-                    give_up.store(true, std::memory_order_relaxed);
                     break;
+                }
+                todo.emplace_back(patch_ptr[size_t(t)], patch_ptr[size_t(t) + 1]);
+                while (!todo.empty()) {
+                    const auto [b, e] = todo.back();
+                    todo.pop_back();
+                    own.assign(patch_rows.begin() + std::ptrdiff_t(b), patch_rows.begin() + std::ptrdiff_t(e));
+                    std::sort(own.begin(), own.end());
+                    if (try_tile(own.data(), int32_t(e - b))) {
+                        emit_tile();
+                        if (!account()) break;
+                    } else if (e - b > 1) {
+                        const int64_t mid = b + (e - b) / 2;
+                        todo.emplace_back(mid, e);
+                        todo.emplace_back(b, mid);
+                    } else {
+                        fail_here();
+                        break;
+                    }
                 }
             }
         }
@@ -782,6 +863,7 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
     P.k = k;
     P.u_cap = u_cap;
     P.l_cap = l_cap;
+    P.patches = patches;
     for (const auto &q : parts) P.fits = P.fits && q.fits;
     if (P.fits) {
         size_t tiles = 0, halo = 0, lidx = 0;
@@ -807,7 +889,7 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
             P.u_max = std::max(P.u_max, q.u_max);
             P.ring.insert(P.ring.end(), q.ring.begin(), q.ring.end());
             for (size_t t = 0; t < q.tile_end.size(); ++t) {
-                P.tile_ptr.push_back(q.tile_end[t]);
+                P.tile_ptr.push_back(patches ? P.tile_ptr.back() + q.tile_end[t] : q.tile_end[t]);
                 P.halo_ptr.push_back(P.halo_ptr.back() + q.halo_n[t]);
                 P.lidx_ptr.push_back(P.lidx_ptr.back() + q.lidx_rows[t]);
             }
@@ -817,20 +899,35 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
             lo += q.lidx.size();
             q = TBPart{};
         }
-        // self-check: tiles cover the rows in order; each updated row's slots
-        // name its CSR neighbours in order, inside the rows valid one sweep
-        // earlier (own + one more ring)
-        if (P.tile_ptr.back() != n) fail(LMS_ERR_STATE, "temporal-blocking plan: tiles do not cover the rows");
+        // self-check: tiles cover the rows in order (patches: every free row
+        // once); each updated row's slots name its CSR neighbours in order,
+        // inside the rows valid one sweep earlier (own + one more ring)
+        if (P.tile_ptr.back() != (patches ? M.n_free : n))
+            fail(LMS_ERR_STATE, "temporal-blocking plan: tiles do not cover the rows");
+        if (patches) {
+            std::vector<uint8_t> seen(size_t(n), 0);
+            for (int32_t t = 0; t < P.tiles; ++t)
+                for (int32_t i = 0; i < P.tile_ptr[size_t(t) + 1] - P.tile_ptr[size_t(t)]; ++i) {
+                    const int32_t v = P.halo[size_t(P.halo_ptr[size_t(t)] + i)];
+                    if (v < 0 || v >= n || M.fixed[size_t(v)] || seen[size_t(v)] ||
+                        (i > 0 && v <= P.halo[size_t(P.halo_ptr[size_t(t)] + i - 1)]))
+                        fail(LMS_ERR_STATE, "temporal-blocking plan: patch rows");
+                    seen[size_t(v)] = 1;
+                }
+        }
         parallel_runs(P.tiles, host_threads(P.tiles), [&](int, int64_t first, int64_t last) {
             for (int64_t t = first; t < last; ++t) {
                 const int32_t b = P.tile_ptr[size_t(t)], e = P.tile_ptr[size_t(t) + 1];
                 const int32_t *r = P.ring.data() + size_t(t) * size_t(k + 1);
                 const int64_t hb = P.halo_ptr[size_t(t)];
                 if (e <= b || r[0] != e - b || r[k] > l_cap || r[k - 1] > u_cap ||
-                    P.halo_ptr[size_t(t) + 1] - hb != int64_t(r[k] - r[0]) ||
+                    P.halo_ptr[size_t(t) + 1] - hb != int64_t(patches ? r[k] : r[k] - r[0]) ||
                     P.lidx_ptr[size_t(t) + 1] - P.lidx_ptr[size_t(t)] != int64_t(r[k - 1]))
                     fail(LMS_ERR_STATE, "temporal-blocking plan: tile counts");
-                auto global_of = [&](int32_t li) { return li < e - b ? b + li : P.halo[size_t(hb + li - (e - b))]; };
+                auto global_of = [&](int32_t li) {
+                    if (patches) return P.halo[size_t(hb + li)];
+                    return li < e - b ? b + li : P.halo[size_t(hb + li - (e - b))];
+                };
                 for (int32_t m = 0; m < k; ++m)
                     for (int32_t li = m == 0 ? 0 : r[m - 1]; li < r[m]; ++li) {
                         const int32_t v = global_of(li);
@@ -858,13 +955,13 @@ namespace {
 
 // Triangle records of a tile plan for the quality evaluated inside the sweep
 // passes.  Every triangle with a free corner belongs to the tile owning its
-// smallest free corner; slot_of(tile, v) gives a staged corner's slot (every
-// corner is staged: the others are neighbours of that free corner).
+// smallest free corner (tile_of(v)); slot_of(tile, v) gives a staged corner's
+// slot (every corner is staged: the others are neighbours of that free corner).
 // Records: slots a | b<<16, c | |T(a)|<<16, |T(b)| | |T(c)|<<16.  Triangles
 // with all corners fixed are listed apart with their weights.  False when a
 // triangle count exceeds 16 bits.
-template <class SlotOf>
-bool tile_quality_records(const Mesh &M, int32_t tiles, const std::vector<int32_t> &tile_ptr, SlotOf slot_of,
+template <class TileOf, class SlotOf>
+bool tile_quality_records(const Mesh &M, int32_t tiles, TileOf tile_of, SlotOf slot_of,
                           std::vector<int64_t> &qtri_ptr, std::vector<uint32_t> &qtri, std::vector<int32_t> &qc_ids,
                           std::vector<double> &qc_w) {
     const int64_t T = M.T;
@@ -879,8 +976,7 @@ bool tile_quality_records(const Mesh &M, int32_t tiles, const std::vector<int32_
             for (int32_t v : c3)
                 if (!M.fixed[size_t(v)] && (own < 0 || v < own)) own = v;
             if (own < 0) continue;
-            const int32_t tile =
-                int32_t(std::upper_bound(tile_ptr.begin(), tile_ptr.end(), own) - tile_ptr.begin()) - 1;
+            const int32_t tile = tile_of(own);
             uint32_t slot[3], cnt[3];
             for (int q = 0; q < 3; ++q) {
                 const int32_t sl = slot_of(tile, c3[q]);
@@ -926,17 +1022,37 @@ void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
     if (!P.fits || P.version != M.version) fail(LMS_ERR_STATE, "quality plan of a stale or unusable tile plan");
     const int32_t k = P.k;
     P.q_built = true;
-    // a corner outside the own rows sits in ring 1 (sorted ascending)
+    // a corner outside the own rows sits in ring 1; both lists are ascending
+    auto find = [](const int32_t *a, int32_t len, int32_t v) -> int32_t {
+        const int32_t *it = std::lower_bound(a, a + len, v);
+        return it == a + len || *it != v ? -1 : int32_t(it - a);
+    };
+    std::vector<int32_t> row_tile;
+    if (P.patches) {
+        row_tile.assign(size_t(M.n), -1);
+        for (int32_t t = 0; t < P.tiles; ++t)
+            for (int64_t i = P.halo_ptr[size_t(t)]; i < P.halo_ptr[size_t(t)] + P.ring[size_t(t) * size_t(k + 1)]; ++i)
+                row_tile[size_t(P.halo[size_t(i)])] = t;
+    }
+    auto tile_of = [&](int32_t v) -> int32_t {
+        if (P.patches) return row_tile[size_t(v)];
+        return int32_t(std::upper_bound(P.tile_ptr.begin(), P.tile_ptr.end(), v) - P.tile_ptr.begin()) - 1;
+    };
     auto slot_of = [&](int32_t tile, int32_t v) -> int32_t {
+        const int32_t *r = P.ring.data() + size_t(tile) * size_t(k + 1);
+        const int32_t *h = P.halo.data() + P.halo_ptr[size_t(tile)];
+        if (P.patches) {
+            const int32_t i = find(h, r[0], v);
+            if (i >= 0) return i;
+            const int32_t j = find(h + r[0], r[1] - r[0], v);
+            return j < 0 ? -1 : r[0] + j;
+        }
         const int32_t b = P.tile_ptr[size_t(tile)], e = P.tile_ptr[size_t(tile) + 1];
         if (v >= b && v < e) return v - b;
-        const int32_t *r = P.ring.data() + size_t(tile) * size_t(k + 1);
-        const int32_t *h1 = P.halo.data() + P.halo_ptr[size_t(tile)];
-        const int32_t n1 = r[1] - r[0];
-        const int32_t *it = std::lower_bound(h1, h1 + n1, v);
-        return it == h1 + n1 || *it != v ? -1 : r[0] + int32_t(it - h1);
+        const int32_t j = find(h, r[1] - r[0], v);
+        return j < 0 ? -1 : r[0] + j;
     };
-    P.q_fits = tile_quality_records(M, P.tiles, P.tile_ptr, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
+    P.q_fits = tile_quality_records(M, P.tiles, tile_of, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
     if (!P.q_fits) return;
     // self-check: slots inside own + ring 1, counts non-zero
     for (int32_t i = 0; i < P.tiles; ++i) {
@@ -963,7 +1079,10 @@ void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P) {
         const int32_t *it = std::lower_bound(h, h + nh, v);
         return it == h + nh || *it != v ? -1 : (e - b) + int32_t(it - h);
     };
-    P.q_fits = tile_quality_records(M, P.tiles, P.tile_ptr, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
+    auto tile_of = [&](int32_t v) -> int32_t {
+        return int32_t(std::upper_bound(P.tile_ptr.begin(), P.tile_ptr.end(), v) - P.tile_ptr.begin()) - 1;
+    };
+    P.q_fits = tile_quality_records(M, P.tiles, tile_of, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
     if (!P.q_fits) return;
     for (int32_t i = 0; i < P.tiles; ++i) {
         const uint32_t nst =

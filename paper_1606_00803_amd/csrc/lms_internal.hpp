@@ -105,16 +105,21 @@ struct Mesh {
     // ring[t*(k+1)+k'-j]; their padded slots (0xFFFF past a row's end) come
     // first in the tile's lidx block.  fits is false when even a one-row
     // tile exceeds the caps (the plan is then empty).
+    // Tiles are either ranges of consecutive rows (patches = false) or
+    // compact patches of free rows grown breadth-first over the adjacency
+    // (patches = true): then the own rows are listed too, ascending, ahead of
+    // the rings in `halo`, and tile_ptr counts own rows.
     struct TBPlan {
         int32_t ts = 0, k = 0, u_cap = 0, l_cap = 0;
+        bool patches = false;
         bool fits = true;
         int32_t tiles = 0;
         int32_t l_max = 0;  // largest staging area (rows), over tiles
         int32_t u_max = 0;  // largest first-sweep update set (rows), over tiles
-        std::vector<int32_t> tile_ptr;  // tiles+1: first own row of each tile
+        std::vector<int32_t> tile_ptr;  // tiles+1: first own row of each tile (patches: prefix of own counts)
         std::vector<int32_t> ring;      // tiles * (k+1)
         std::vector<int64_t> halo_ptr;  // tiles+1, into halo
-        std::vector<int32_t> halo;      // per tile: rings 1..k
+        std::vector<int32_t> halo;      // per tile: rings 1..k (patches: own rows, then rings 1..k)
         std::vector<int64_t> lidx_ptr;  // tiles+1, in rows of ell_w slots
         std::vector<uint16_t> lidx;
         // Quality of each staged state (filled by tb_quality_plan): every
@@ -187,7 +192,7 @@ void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std
                    std::vector<int32_t> trec, std::vector<int32_t> tmesh, std::vector<int32_t> vt_ptr,
                    std::vector<int32_t> vt);
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
-const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap);
+const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap, bool patches = false);
 void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
 const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap);
 void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P);
