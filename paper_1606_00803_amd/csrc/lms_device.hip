@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1732,9 +1733,19 @@ constexpr int kDefaultSweepConfig = 0;
     TB(65, 256, 8, 4, 0, 512, 2, 2048, 1)    \
     TB(66, 256, 8, 4, 16, 256, 3, 1024, 1)   \
     TB(67, 256, 8, 8, 0, 512, 4, 2048, 1)    \
-    TB(68, 512, 8, 4, 0, 512, 4, 2048, 1)
+    TB(68, 512, 8, 4, 0, 512, 4, 2048, 1)    \
+    TB(69, 512, 8, 4, 16, 512, 4, 2048, 1)   \
+    TB(70, 512, 8, 4, 0, 512, 3, 2048, 1)    \
+    TB(71, 512, 8, 4, 0, 768, 4, 2048, 1)    \
+    TB(72, 256, 8, 4, 16, 256, 4, 1024, 1)   \
+    TB(73, 1024, 8, 2, 0, 1024, 4, 2048, 1)  \
+    TB(74, 1024, 8, 2, 16, 1024, 4, 2048, 1) \
+    TB(75, 1024, 8, 3, 0, 1536, 4, 3072, 1)  \
+    TB(76, 1024, 8, 4, 0, 2048, 4, 4096, 1)  \
+    TB(77, 1024, 8, 3, 0, 1024, 6, 3072, 1)  \
+    TB(78, 1024, 8, 4, 0, 1024, 8, 4096, 1)
 constexpr int kFirstTBConfig = kNumSweepConfigs;
-constexpr int kNumAllConfigs = 69;
+constexpr int kNumAllConfigs = 79;
 static_assert(kNumAllConfigs <= 80, "tune_us holds 80 variants");
 
 struct TBShape {
@@ -1931,7 +1942,12 @@ const DeviceState::TBDev *find_tb(const DeviceState &d, const TBShape &t) {
 // Build (host) and upload the temporal-blocking plan of variant shape t.
 const DeviceState::TBDev &ensure_tb(DeviceState &d, Mesh &M, const TBShape &t) {
     if (const DeviceState::TBDev *h = find_tb(d, t)) return *h;
+    const auto t0 = std::chrono::steady_clock::now();
     const Mesh::TBPlan &P = tb_plan(M, t.ts, t.k, t.bs * t.r, t.lcap, t.g != 0);
+    if (env_flag("LMS_VERBOSE", false))
+        std::fprintf(stderr, "[lms] tile plan %s ts=%d k=%d: %d tiles, %s, %.2f s\n", t.g ? "patches" : "ranges", t.ts,
+                     t.k, P.tiles, P.fits ? "fits" : "does not fit",
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     DeviceState::TBDev h;
     h.ts = t.ts;
     h.k = t.k;
@@ -2239,6 +2255,7 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
         it = keep_ts(it->ts) ? std::next(it) : M.halo_plans.erase(it);
     for (auto it = M.tb_plans.begin(); it != M.tb_plans.end();)
         it = keep_tb(it->ts, it->k, it->u_cap, it->l_cap, it->patches) ? std::next(it) : M.tb_plans.erase(it);
+    M.patch_sets.clear();  // only needed to build plans; a later tuning grows them again
 }
 
 // Autotuner: time every sweep variant on this mesh (src -> dst, which leaves
@@ -2276,8 +2293,26 @@ void tune_sweep(DeviceState &d, Mesh &M, const T *sx, const T *sy, T *dx, T *dy,
     float best_ms = 3.0e38f, best_all_ms = 3.0e38f, best_tb_ms = 3.0e38f;  // per sweep
     hipError_t err = hipSuccess;
     vec2_t<T> *pa = nullptr, *pb = nullptr;
+    // From 4M rows on, the tuner times fewer temporally blocked variants:
+    // each plan costs ~30-40 bytes per row on the host and the device, and
+    // growing the patches of one tile size is a pass over the mesh whose
+    // accesses follow the ordering (tens of seconds for a random ordering
+    // at 64M rows).  There it skips variants over row ranges where patch
+    // variants of the same padded width exist (patches won wherever both
+    // were measured), and patch variants with tiles under 1024 or over 1536
+    // rows (the larger tiles won on every mesh of 16M rows or more).
+    auto has_patches = [](int w) {
+        for (int c = kFirstTBConfig; c < kNumAllConfigs; ++c)
+            if (tb_shape(c).g && tb_shape(c).w == w) return true;
+        return false;
+    };
+    auto skip_large = [&](int c) {
+        if (M.n < kDropPlansFrom || !is_tb_config(c)) return false;
+        const TBShape t = tb_shape(c);
+        return t.g ? (t.ts < 1024 || t.ts > 1536) : has_patches(t.w);
+    };
     for (int c = 0; c < kNumAllConfigs && err == hipSuccess; ++c) {
-        if (!sweep_config_usable<T>(c, d, M)) {
+        if (skip_large(c) || !sweep_config_usable<T>(c, d, M)) {
             d.tune_us[pi][c] = -1.f;
             continue;
         }

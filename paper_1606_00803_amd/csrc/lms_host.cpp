@@ -521,6 +521,7 @@ void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std
     M.halo_plans.clear();
     M.tb_plans.clear();
     M.mc_plans.clear();
+    M.patch_sets.clear();
     M.ordering = kind;
     M.new2old = std::move(new2old);
     M.old2new = std::move(old2new);
@@ -694,9 +695,16 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
     // over the adjacency (one pass over the mesh; a patch may reach rows of
     // any label, which gathers the scattered end of an ordering into the
     // patches around it).  patch_rows lists each patch in that order.
-    std::vector<int64_t> patch_ptr(1, 0);
-    std::vector<int32_t> patch_rows;
-    if (patches) {
+    const Mesh::Patches *ps = nullptr;
+    for (const auto &q : M.patch_sets)
+        if (patches && q.ts == ts && q.version == M.version) ps = &q;
+    if (patches && !ps) {
+        M.patch_sets.emplace_back();
+        Mesh::Patches &q = M.patch_sets.back();
+        q.ts = ts;
+        std::vector<int64_t> &patch_ptr = q.patch_ptr;
+        std::vector<int32_t> &patch_rows = q.patch_rows;
+        patch_ptr.assign(1, 0);
         std::vector<uint8_t> taken(size_t(n), 0);
         resize_or_fail(patch_rows, size_t(M.n_free));
         patch_rows.clear();
@@ -720,7 +728,13 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
             patch_rows.insert(patch_rows.end(), grow.begin(), grow.end());
             patch_ptr.push_back(int64_t(patch_rows.size()));
         }
+        q.version = M.version;
+        ps = &q;
     }
+    static const std::vector<int64_t> no_ptr(1, 0);
+    static const std::vector<int32_t> no_rows;
+    const std::vector<int64_t> &patch_ptr = ps ? ps->patch_ptr : no_ptr;
+    const std::vector<int32_t> &patch_rows = ps ? ps->patch_rows : no_rows;
     const int64_t items = patches ? int64_t(patch_ptr.size()) - 1 : nominal;
     const int workers = host_threads(items);
     std::vector<TBPart> parts(static_cast<size_t>(workers));

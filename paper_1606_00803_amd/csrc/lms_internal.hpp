@@ -137,6 +137,15 @@ struct Mesh {
         uint64_t version = ~uint64_t(0);
     };
     std::deque<TBPlan> tb_plans;
+    // breadth-first patches of up to ts free rows (shared by the plans of one
+    // tile size): rows of patch i at patch_rows[patch_ptr[i] .. patch_ptr[i+1])
+    struct Patches {
+        int32_t ts = 0;
+        uint64_t version = ~uint64_t(0);
+        std::vector<int64_t> patch_ptr;
+        std::vector<int32_t> patch_rows;
+    };
+    std::deque<Patches> patch_sets;
 
     // Tile plan of the multicolour sweep in one pass (all colours of one
     // sweep, tile by tile, in LDS).  Tiles are row ranges (ts rows, halved

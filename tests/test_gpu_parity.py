@@ -510,7 +510,7 @@ def test_temporal_blocking_same_bits_as_single_sweeps(kind):
                 os.environ["LMS_SWEEP_CONFIG"] = "36"       # one sweep per pass (halo-staged)
                 rx, ry, _, _ = run_library(m, kind, K, dtype=dt, M=M)
                 ran = 0
-                for cfg in (*range(44, 56), *range(64, 69)):  # width 8: depths 2 to 4, ranges and patches
+                for cfg in (*range(44, 56), *range(64, 79)):  # width 8: depths 2 to 8, ranges and patches
                     os.environ["LMS_SWEEP_CONFIG"] = str(cfg)
                     try:
                         x, y, r, _ = run_library(m, kind, K, dtype=dt, M=M)
