@@ -39,7 +39,8 @@ RANDOM_SEED = 1002
 METRIC = "vertex-updates/sec and % HBM roofline per ordering (ORI/BFS/RDR/random), FP64 vs FP32"
 COUNTERS = {"ocean": os.path.join(ROOT, "profiles", "sweep_ocean_rdr_f64_counters.md"),
             "graded16m": os.path.join(ROOT, "profiles", "sweep_graded16m_counters.md")}
-DEVICE_SRC = os.path.join(ROOT, "paper_1606_00803_amd", "csrc", "lms_device.hip")
+# the kernels' source: counter summaries taken on other kernel code are not used
+DEVICE_SRC = os.path.join(ROOT, "paper_1606_00803_amd", "csrc", "lms_kernels.hpp")
 
 
 def log(*a):
@@ -71,7 +72,7 @@ def counters_traffic(kernel_name, prec, path):
         text = open(path).read()
     except OSError:
         return None
-    src = re.search(r"^- source_sha256: (\S+)$", text, flags=re.M)
+    src = re.search(r"^- source_sha256: (\S+)", text, flags=re.M)
     if not src or src.group(1) != device_source_hash():
         return None
     for name, p, traffic in re.findall(r"^\| `(\S+)` \| (f64|f32) \|[^|]*\| (\d+) \|", text, flags=re.M):

@@ -222,7 +222,10 @@ lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_p
  * have at most 4096 vertices, the last fixed-K Jacobi call may have run every
  * sweep in one launch (one workgroup per mesh); the name then starts with
  * "small/r<rows per thread>/one-launch".  The first such call times that
- * kernel against the tuned per-sweep path and keeps the faster.  buf: host
+ * kernel against the tuned per-sweep path and keeps the faster.  Once the
+ * stopping rule has run with the quality fused into temporally blocked
+ * passes, " stop=<variant>" names the variant it timed fastest in that form.
+ * buf: host
  * char[len] out, NUL-terminated, truncated to len-1 characters. */
 lms_status lms_sweep_config(lms_mesh_t m, lms_precision p, char *buf, int32_t len);
 
