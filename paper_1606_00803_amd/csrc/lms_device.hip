@@ -87,6 +87,7 @@ struct DeviceState {
     std::deque<TBDev> tbs;       // uploaded temporal-blocking plans of the current version
     struct MCDev {
         int32_t ts = 0, l_cap = 0, u_cap = 0, tiles = 0, l_max = 0, colors = 0;
+        bool patches = false;
         bool fits = false;
         int32_t *tile_ptr = nullptr, *halo = nullptr;
         int64_t *halo_ptr = nullptr, *upd_ptr = nullptr;
@@ -792,27 +793,38 @@ vec2_t<T> *ensure_packed(DeviceState &d, int which, int32_t n) {
 }
 
 // One-pass multicolour variants: MC(id, tile size, staging cap, updated
-// rows per thread R (256 threads), map).
-#define LMS_MC_CONFIGS(MC)        \
-    MC(0, 128, 1024, 2, 16)       \
-    MC(1, 128, 1024, 2, 0)        \
-    MC(2, 256, 2048, 4, 16)       \
-    MC(3, 64, 512, 1, 16)
-constexpr int kNumMcConfigs = 4;
+// rows per thread R (256 threads), map, patches).  patches = 1: tiles are
+// breadth-first patches of free rows, as for the temporally blocked sweep.
+#define LMS_MC_CONFIGS(MC)          \
+    MC(0, 128, 1024, 2, 16, 0)      \
+    MC(1, 128, 1024, 2, 0, 0)       \
+    MC(2, 256, 2048, 4, 16, 0)      \
+    MC(3, 64, 512, 1, 16, 0)        \
+    MC(4, 256, 1024, 2, 16, 1)      \
+    MC(5, 512, 2048, 4, 0, 1)       \
+    MC(6, 512, 2048, 4, 16, 1)      \
+    MC(7, 1024, 4096, 8, 0, 1)
+constexpr int kNumMcConfigs = 8;
 
 struct MCShape {
-    int ts = 0, lcap = 0, r = 0, map = 0;
+    int ts = 0, lcap = 0, r = 0, map = 0, g = 0;
 };
 
 MCShape mc_shape(int cfg) {
     switch (cfg) {
-#define MC(id, ts, lcap, r, map) \
-    case id:                     \
-        return MCShape{ts, lcap, r, map};
+#define MC(id, ts, lcap, r, map, g) \
+    case id:                        \
+        return MCShape{ts, lcap, r, map, g};
         LMS_MC_CONFIGS(MC)
 #undef MC
     }
     return MCShape{};
+}
+
+// Whether a resident multicolour plan is the one of shape t.
+template <class P>
+bool mc_plan_is(const P &p, const MCShape &t) {
+    return p.ts == t.ts && p.l_cap == t.lcap && p.u_cap == 256 * t.r && p.patches == (t.g != 0);
 }
 
 // Meshes from this many rows on drop, after each tuning, the tile plans that
@@ -873,16 +885,13 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
         it = d.tbs.erase(it);
     }
     // one-pass multicolour plans: keep the tuned precisions' choices
-    auto keep_mc = [&](int32_t ts, int32_t l_cap, int32_t u_cap) {
+    auto keep_mc = [&](const auto &plan) {
         for (int pi = 0; pi < 2; ++pi)
-            if (d.mc_cfg[pi] >= 0) {
-                const MCShape t = mc_shape(d.mc_cfg[pi]);
-                if (t.ts == ts && t.lcap == l_cap && 256 * t.r == u_cap) return true;
-            }
+            if (d.mc_cfg[pi] >= 0 && mc_plan_is(plan, mc_shape(d.mc_cfg[pi]))) return true;
         return false;
     };
     for (auto it = d.mcs.begin(); it != d.mcs.end();) {
-        if (keep_mc(it->ts, it->l_cap, it->u_cap)) {
+        if (keep_mc(*it)) {
             ++it;
             continue;
         }
@@ -896,7 +905,7 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
         it = d.mcs.erase(it);
     }
     for (auto it = M.mc_plans.begin(); it != M.mc_plans.end();)
-        it = keep_mc(it->ts, it->l_cap, it->u_cap) ? std::next(it) : M.mc_plans.erase(it);
+        it = keep_mc(*it) ? std::next(it) : M.mc_plans.erase(it);
     for (auto it = M.halo_plans.begin(); it != M.halo_plans.end();)
         it = keep_ts(it->ts) ? std::next(it) : M.halo_plans.erase(it);
     for (auto it = M.tb_plans.begin(); it != M.tb_plans.end();)
@@ -1371,12 +1380,18 @@ void tune_fused_stop(DeviceState &d, Mesh &M, const T *x, const T *y, hipStream_
 
 const DeviceState::MCDev &ensure_mc(DeviceState &d, Mesh &M, const MCShape &t) {
     for (const auto &h : d.mcs)
-        if (h.ts == t.ts && h.l_cap == t.lcap && h.u_cap == 256 * t.r) return h;
-    const Mesh::MCPlan &P = mc_plan(M, t.ts, t.lcap, 256 * t.r);
+        if (mc_plan_is(h, t)) return h;
+    const auto t0 = std::chrono::steady_clock::now();
+    const Mesh::MCPlan &P = mc_plan(M, t.ts, t.lcap, 256 * t.r, t.g != 0);
+    if (env_flag("LMS_VERBOSE", false))
+        std::fprintf(stderr, "[lms] multicolour plan %s ts=%d: %d tiles, %s, %.2f s\n", t.g ? "patches" : "ranges",
+                     t.ts, P.tiles, P.fits ? "fits" : "does not fit",
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     DeviceState::MCDev h;
     h.ts = t.ts;
     h.l_cap = t.lcap;
     h.u_cap = 256 * t.r;
+    h.patches = t.g != 0;
     h.fits = P.fits;
     h.tiles = P.tiles;
     h.l_max = P.l_max;
@@ -1401,6 +1416,22 @@ bool mc_usable(DeviceState &d, Mesh &M, int cfg) {
     return h.fits && h.tiles > 0 && size_t(h.l_max) * sizeof(vec2_t<T>) <= size_t(64) * 1024;
 }
 
+// The plain and quality-fused kernels of one-pass multicolour variant cfg
+// at padded width W, handed to go.
+template <typename T, int W, class Go>
+void mc_dispatch(int cfg, Go &&go) {
+    switch (cfg) {
+#define MC(id, ts, lcap, r, map, g)                                                                   \
+    case id:                                                                                          \
+        go(k_colour_tiles<T, 256, W, r, map, false, g != 0>, k_colour_tiles<T, 256, W, r, map, true, g != 0>); \
+        break;
+        LMS_MC_CONFIGS(MC)
+#undef MC
+        default:
+            fail(LMS_ERR_STATE, "unknown one-pass multicolour variant");
+    }
+}
+
 // One multicolour sweep src -> dst in one pass of variant cfg.
 template <typename T>
 void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst,
@@ -1408,7 +1439,7 @@ void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src,
     const MCShape t = mc_shape(cfg);
     const DeviceState::MCDev *h = nullptr;
     for (const auto &x : d.mcs)
-        if (x.ts == t.ts && x.l_cap == t.lcap && x.u_cap == 256 * t.r) h = &x;
+        if (mc_plan_is(x, t)) h = &x;
     if (!h || !h->fits || h->colors != M.n_colors) fail(LMS_ERR_STATE, "one-pass multicolour variant without its plan");
     if (size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024) fail(LMS_ERR_STATE, "multicolour plan too large");
     if (qual && (!h->q_ready || !h->q_fits || !st)) fail(LMS_ERR_STATE, "quality-fused multicolour pass without its plan");
@@ -1421,28 +1452,19 @@ void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src,
             plain<<<h->tiles, 256, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
                                              h->colors, src, dst, st, nullptr, nullptr, nullptr, 0);
     };
-#define LMS_MC_W(W)                                                                                    \
-    switch (cfg) {                                                                                     \
-        case 0: go(k_colour_tiles<T, 256, W, 2, 16, false>, k_colour_tiles<T, 256, W, 2, 16, true>); break; \
-        case 1: go(k_colour_tiles<T, 256, W, 2, 0, false>, k_colour_tiles<T, 256, W, 2, 0, true>); break;   \
-        case 2: go(k_colour_tiles<T, 256, W, 4, 16, false>, k_colour_tiles<T, 256, W, 4, 16, true>); break; \
-        case 3: go(k_colour_tiles<T, 256, W, 1, 16, false>, k_colour_tiles<T, 256, W, 1, 16, true>); break; \
-        default: fail(LMS_ERR_STATE, "unknown one-pass multicolour variant");                           \
-    }
     switch (M.ell_w) {
         case 8:
-            LMS_MC_W(8)
+            mc_dispatch<T, 8>(cfg, go);
             break;
         case 12:
-            LMS_MC_W(12)
+            mc_dispatch<T, 12>(cfg, go);
             break;
         case 16:
-            LMS_MC_W(16)
+            mc_dispatch<T, 16>(cfg, go);
             break;
         default:
             fail(LMS_ERR_STATE, "no padded adjacency for the one-pass multicolour sweep");
     }
-#undef LMS_MC_W
     launch_check();
 }
 
@@ -1507,12 +1529,12 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
 bool ensure_mcq(DeviceState &d, Mesh &M, const MCShape &t) {
     DeviceState::MCDev *h = nullptr;
     for (auto &x : d.mcs)
-        if (x.ts == t.ts && x.l_cap == t.lcap && x.u_cap == 256 * t.r) h = &x;
+        if (mc_plan_is(x, t)) h = &x;
     if (!h || !h->fits) fail(LMS_ERR_STATE, "quality-fused multicolour pass without its tile plan");
     if (h->q_ready) return h->q_fits;
     Mesh::MCPlan *P = nullptr;
     for (auto &p : M.mc_plans)
-        if (p.ts == t.ts && p.l_cap == t.lcap && p.u_cap == 256 * t.r && p.version == M.version) P = &p;
+        if (mc_plan_is(p, t) && p.version == M.version) P = &p;
     if (!P) fail(LMS_ERR_STATE, "multicolour tile plan missing on the host");
     mc_quality_plan(M, *P);
     h->q_ready = true;
@@ -1641,7 +1663,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         const MCShape t = mc_shape(mc);
         const DeviceState::MCDev *h = nullptr;
         for (const auto &xh : d.mcs)
-            if (xh.ts == t.ts && xh.l_cap == t.lcap && xh.u_cap == 256 * t.r) h = &xh;
+            if (mc_plan_is(xh, t)) h = &xh;
         k_stop_reset<<<1, 64, 0, s>>>(d.st);
         k_qconst<T><<<1, 256, 0, s>>>(h->qc_ids, h->qc_w, h->n_qc, A, d.st);
         launch_check();

@@ -680,6 +680,46 @@ struct TBPart {
 
 }  // namespace
 
+// Patches: seeds in ascending label order; from each free row not yet
+// taken, take up to ts free rows not yet taken, in breadth-first order over
+// the adjacency (one pass over the mesh; a patch may reach rows of any
+// label, which gathers the scattered end of an ordering into the patches
+// around it).  Cached per tile size until the plans are dropped.
+const Mesh::Patches &patch_set(Mesh &M, int32_t ts) {
+    for (const auto &q : M.patch_sets)
+        if (q.ts == ts && q.version == M.version) return q;
+    const int32_t n = M.n;
+    Mesh::Patches q;
+    q.ts = ts;
+    q.patch_ptr.assign(1, 0);
+    resize_or_fail(q.patch_rows, size_t(M.n_free));
+    q.patch_rows.clear();
+    std::vector<uint8_t> taken(size_t(n), 0);
+    std::vector<int32_t> grow;
+    for (int32_t seed = 0; seed < n; ++seed) {
+        if (M.fixed[size_t(seed)] || taken[size_t(seed)]) continue;
+        grow.assign(1, seed);
+        taken[size_t(seed)] = 1;
+        for (size_t h = 0; h < grow.size() && h < size_t(ts); ++h) {
+            const int32_t v = grow[h];
+            for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                const int32_t u = M.col[size_t(j)];
+                if (!M.fixed[size_t(u)] && !taken[size_t(u)]) {
+                    taken[size_t(u)] = 1;
+                    grow.push_back(u);
+                }
+            }
+        }
+        for (size_t i = size_t(ts); i < grow.size(); ++i) taken[size_t(grow[i])] = 0;  // give the rest back
+        grow.resize(std::min(grow.size(), size_t(ts)));
+        q.patch_rows.insert(q.patch_rows.end(), grow.begin(), grow.end());
+        q.patch_ptr.push_back(int64_t(q.patch_rows.size()));
+    }
+    q.version = M.version;
+    M.patch_sets.push_back(std::move(q));
+    return M.patch_sets.back();
+}
+
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap, bool patches) {
     for (const auto &h : M.tb_plans)
         if (h.ts == ts && h.k == k && h.u_cap == u_cap && h.l_cap == l_cap && h.patches == patches &&
@@ -690,51 +730,10 @@ const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32
         fail(LMS_ERR_ARG, "temporal-blocking plan: bad tile size, depth or caps");
     const int32_t n = M.n, W = M.ell_w;
     const int64_t nominal = (int64_t(n) + ts - 1) / ts;
-    // Patches: seeds in ascending label order; from each free row not yet
-    // taken, take up to ts free rows not yet taken, in breadth-first order
-    // over the adjacency (one pass over the mesh; a patch may reach rows of
-    // any label, which gathers the scattered end of an ordering into the
-    // patches around it).  patch_rows lists each patch in that order.
-    const Mesh::Patches *ps = nullptr;
-    for (const auto &q : M.patch_sets)
-        if (patches && q.ts == ts && q.version == M.version) ps = &q;
-    if (patches && !ps) {
-        M.patch_sets.emplace_back();
-        Mesh::Patches &q = M.patch_sets.back();
-        q.ts = ts;
-        std::vector<int64_t> &patch_ptr = q.patch_ptr;
-        std::vector<int32_t> &patch_rows = q.patch_rows;
-        patch_ptr.assign(1, 0);
-        std::vector<uint8_t> taken(size_t(n), 0);
-        resize_or_fail(patch_rows, size_t(M.n_free));
-        patch_rows.clear();
-        std::vector<int32_t> grow;
-        for (int32_t seed = 0; seed < n; ++seed) {
-            if (M.fixed[size_t(seed)] || taken[size_t(seed)]) continue;
-            grow.assign(1, seed);
-            taken[size_t(seed)] = 1;
-            for (size_t h = 0; h < grow.size() && h < size_t(ts); ++h) {
-                const int32_t v = grow[h];
-                for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
-                    const int32_t u = M.col[size_t(j)];
-                    if (!M.fixed[size_t(u)] && !taken[size_t(u)]) {
-                        taken[size_t(u)] = 1;
-                        grow.push_back(u);
-                    }
-                }
-            }
-            for (size_t i = size_t(ts); i < grow.size(); ++i) taken[size_t(grow[i])] = 0;  // give the rest back
-            grow.resize(std::min(grow.size(), size_t(ts)));
-            patch_rows.insert(patch_rows.end(), grow.begin(), grow.end());
-            patch_ptr.push_back(int64_t(patch_rows.size()));
-        }
-        q.version = M.version;
-        ps = &q;
-    }
-    static const std::vector<int64_t> no_ptr(1, 0);
-    static const std::vector<int32_t> no_rows;
-    const std::vector<int64_t> &patch_ptr = ps ? ps->patch_ptr : no_ptr;
-    const std::vector<int32_t> &patch_rows = ps ? ps->patch_rows : no_rows;
+    static const Mesh::Patches no_patches{0, 0, std::vector<int64_t>(1, 0), {}};
+    const Mesh::Patches &ps = patches ? patch_set(M, ts) : no_patches;
+    const std::vector<int64_t> &patch_ptr = ps.patch_ptr;
+    const std::vector<int32_t> &patch_rows = ps.patch_rows;
     const int64_t items = patches ? int64_t(patch_ptr.size()) - 1 : nominal;
     const int workers = host_threads(items);
     std::vector<TBPart> parts(static_cast<size_t>(workers));
@@ -1084,23 +1083,42 @@ void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P) {
     if (P.q_built) return;
     if (!P.fits || P.version != M.version) fail(LMS_ERR_STATE, "quality plan of a stale or unusable tile plan");
     P.q_built = true;
-    // a corner outside the own rows sits in the tile's staged list (ascending)
+    // a corner outside the own rows sits in the tile's other staged rows;
+    // both lists are ascending (a patch lists its own rows ahead of them)
+    auto find = [](const int32_t *a, int32_t len, int32_t v) -> int32_t {
+        const int32_t *it = std::lower_bound(a, a + len, v);
+        return it == a + len || *it != v ? -1 : int32_t(it - a);
+    };
+    std::vector<int32_t> row_tile;
+    if (P.patches) {
+        row_tile.assign(size_t(M.n), -1);
+        for (int32_t t = 0; t < P.tiles; ++t)
+            for (int32_t i = 0; i < P.tile_ptr[size_t(t) + 1] - P.tile_ptr[size_t(t)]; ++i)
+                row_tile[size_t(P.halo[size_t(P.halo_ptr[size_t(t)] + i)])] = t;
+    }
     auto slot_of = [&](int32_t tile, int32_t v) -> int32_t {
-        const int32_t b = P.tile_ptr[size_t(tile)], e = P.tile_ptr[size_t(tile) + 1];
-        if (v >= b && v < e) return v - b;
+        const int32_t b = P.tile_ptr[size_t(tile)], e = P.tile_ptr[size_t(tile) + 1], nown = e - b;
         const int32_t *h = P.halo.data() + P.halo_ptr[size_t(tile)];
         const int32_t nh = int32_t(P.halo_ptr[size_t(tile) + 1] - P.halo_ptr[size_t(tile)]);
-        const int32_t *it = std::lower_bound(h, h + nh, v);
-        return it == h + nh || *it != v ? -1 : (e - b) + int32_t(it - h);
+        if (P.patches) {
+            const int32_t i = find(h, nown, v);
+            if (i >= 0) return i;
+            const int32_t j = find(h + nown, nh - nown, v);
+            return j < 0 ? -1 : nown + j;
+        }
+        if (v >= b && v < e) return v - b;
+        const int32_t j = find(h, nh, v);
+        return j < 0 ? -1 : nown + j;
     };
     auto tile_of = [&](int32_t v) -> int32_t {
+        if (P.patches) return row_tile[size_t(v)];
         return int32_t(std::upper_bound(P.tile_ptr.begin(), P.tile_ptr.end(), v) - P.tile_ptr.begin()) - 1;
     };
     P.q_fits = tile_quality_records(M, P.tiles, tile_of, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
     if (!P.q_fits) return;
     for (int32_t i = 0; i < P.tiles; ++i) {
-        const uint32_t nst =
-            uint32_t(P.tile_ptr[size_t(i) + 1] - P.tile_ptr[size_t(i)] + P.halo_ptr[size_t(i) + 1] - P.halo_ptr[size_t(i)]);
+        const uint32_t nst = uint32_t(P.halo_ptr[size_t(i) + 1] - P.halo_ptr[size_t(i)]) +
+                             uint32_t(P.patches ? 0 : P.tile_ptr[size_t(i) + 1] - P.tile_ptr[size_t(i)]);
         for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t) {
             const uint32_t w0 = P.qtri[size_t(3 * t)], w1 = P.qtri[size_t(3 * t + 1)], w2 = P.qtri[size_t(3 * t + 2)];
             if ((w0 & 0xFFFFu) >= nst || (w0 >> 16) >= nst || (w1 & 0xFFFFu) >= nst || (w1 >> 16) == 0 ||
@@ -1110,13 +1128,16 @@ void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P) {
     }
 }
 
-const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
+const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, bool patches) {
     for (const auto &h : M.mc_plans)
-        if (h.ts == ts && h.l_cap == l_cap && h.u_cap == u_cap && h.version == M.version) return h;
+        if (h.ts == ts && h.l_cap == l_cap && h.u_cap == u_cap && h.patches == patches && h.version == M.version)
+            return h;
     if (M.ell_w <= 0) fail(LMS_ERR_STATE, "no padded adjacency for a multicolour tile plan");
     if (ts <= 0 || l_cap < 1 || l_cap >= 0xFFFF || u_cap < 1) fail(LMS_ERR_ARG, "multicolour plan: bad tile size or cap");
     const int32_t n = M.n, W = M.ell_w, C = M.n_colors;
-    const int64_t nominal = (int64_t(n) + ts - 1) / ts;
+    static const Mesh::Patches no_patches{0, 0, std::vector<int64_t>(1, 0), {}};
+    const Mesh::Patches &ps = patches ? patch_set(M, ts) : no_patches;
+    const int64_t nominal = patches ? int64_t(ps.patch_ptr.size()) - 1 : (int64_t(n) + ts - 1) / ts;
     struct Part {
         bool fits = true;
         std::vector<int32_t> tile_end, halo, halo_n;
@@ -1134,15 +1155,16 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
         SlotMap slots(size_t(l_cap) + size_t(W) + 1);
         std::vector<int32_t> staged, upd, queue;
         std::vector<uint8_t> in_upd_mark;  // parallel to staged: updated here
-        // Stage [b, e): own rows, the closure of updated rows, their
+        // Stage the own rows (ascending), the closure of updated rows, their
         // neighbours; false when the staging area passes the cap.
-        auto try_tile = [&](int32_t b, int32_t e) {
+        auto try_tile = [&](const int32_t *own, int32_t nown) {
             slots.clear();
             staged.clear();
             in_upd_mark.clear();
             queue.clear();
-            for (int32_t v = b; v < e; ++v) {
-                slots.insert(v, v - b);
+            for (int32_t i = 0; i < nown; ++i) {
+                const int32_t v = own[i];
+                slots.insert(v, i);
                 staged.push_back(v);
                 in_upd_mark.push_back(M.fixed[size_t(v)] ? 0 : 1);
                 if (!M.fixed[size_t(v)]) queue.push_back(v);
@@ -1172,8 +1194,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
             }
             return int64_t(queue.size()) <= u_cap;
         };
-        auto emit_tile = [&](int32_t b, int32_t e) {
-            const int32_t nown = e - b;
+        auto emit_tile = [&](const int32_t *own, int32_t nown) {
             // slots: own rows, then the others in ascending id
             std::vector<int32_t> others(staged.begin() + nown, staged.end());
             std::sort(others.begin(), others.end());
@@ -1190,7 +1211,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
                 std::sort(rows.begin(), rows.end());
                 out.ucount.push_back(int64_t(rows.size()));
                 for (int32_t sl : rows) {
-                    const int32_t v = sl < nown ? b + sl : others[size_t(sl - nown)];
+                    const int32_t v = sl < nown ? own[sl] : others[size_t(sl - nown)];
                     out.urow.push_back(uint16_t(sl));
                     const size_t base = out.uidx.size();
                     out.uidx.resize(base + size_t(W), uint16_t(0xFFFF));
@@ -1201,23 +1222,34 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
                     }
                 }
             }
-            out.tile_end.push_back(e);
+            // patches list their own rows ahead of the other staged rows
+            out.tile_end.push_back(patches ? nown : own[nown - 1] + 1);
+            if (patches) out.halo.insert(out.halo.end(), own, own + nown);
             out.halo.insert(out.halo.end(), others.begin(), others.end());
-            out.halo_n.push_back(int32_t(others.size()));
+            out.halo_n.push_back(int32_t(others.size()) + (patches ? nown : 0));
             out.l_max = std::max(out.l_max, int32_t(staged.size()));
         };
-        std::vector<std::pair<int32_t, int32_t>> todo;
+        // a range tile is halved in the middle, a patch along its
+        // breadth-first order (the first half is a smaller ball around the seed)
+        std::vector<std::pair<int64_t, int64_t>> todo;
+        std::vector<int32_t> ownv;
         for (int64_t t = first; t < last && out.fits; ++t) {
             if (give_up.load(std::memory_order_relaxed)) {
                 out.fits = false;
                 break;
             }
-            todo.emplace_back(int32_t(t * ts), int32_t(std::min<int64_t>(n, (t + 1) * ts)));
+            if (patches)
+                todo.emplace_back(ps.patch_ptr[size_t(t)], ps.patch_ptr[size_t(t) + 1]);
+            else
+                todo.emplace_back(t * ts, std::min<int64_t>(n, (t + 1) * ts));
             while (!todo.empty()) {
                 const auto [b, e] = todo.back();
                 todo.pop_back();
-                if (try_tile(b, e)) {
-                    emit_tile(b, e);
+                ownv.resize(size_t(e - b));
+                for (int64_t i = b; i < e; ++i) ownv[size_t(i - b)] = patches ? ps.patch_rows[size_t(i)] : int32_t(i);
+                if (patches) std::sort(ownv.begin(), ownv.end());
+                if (try_tile(ownv.data(), int32_t(e - b))) {
+                    emit_tile(ownv.data(), int32_t(e - b));
                     const int64_t own = all_own.fetch_add(e - b) + (e - b);
                     const int64_t st = all_staged.fetch_add(int64_t(staged.size())) + int64_t(staged.size());
                     if (own > sample && st > kTBMaxStagedPerRow * own) {  // the same bound as temporal blocking
@@ -1226,7 +1258,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
                         break;
                     }
                 } else if (e - b > 1) {
-                    const int32_t mid = b + (e - b) / 2;
+                    const int64_t mid = b + (e - b) / 2;
                     todo.emplace_back(mid, e);
                     todo.emplace_back(b, mid);
                 } else {
@@ -1241,6 +1273,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
     P.ts = ts;
     P.l_cap = l_cap;
     P.u_cap = u_cap;
+    P.patches = patches;
     P.colors = C;
     for (const auto &q : parts) P.fits = P.fits && q.fits;
     if (P.fits) {
@@ -1250,7 +1283,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
         for (auto &q : parts) {
             P.l_max = std::max(P.l_max, q.l_max);
             for (size_t t = 0; t < q.tile_end.size(); ++t) {
-                P.tile_ptr.push_back(q.tile_end[t]);
+                P.tile_ptr.push_back(patches ? P.tile_ptr.back() + q.tile_end[t] : q.tile_end[t]);
                 P.halo_ptr.push_back(P.halo_ptr.back() + q.halo_n[t]);
             }
             for (int64_t c : q.ucount) P.upd_ptr.push_back(P.upd_ptr.back() + c);
@@ -1265,14 +1298,28 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
         for (int32_t t = 0; t < P.tiles; ++t)
             for (int32_t c = 0; c <= C; ++c) up[size_t(t) * size_t(C + 1) + size_t(c)] = P.upd_ptr[size_t(t) * size_t(C) + size_t(c)];
         P.upd_ptr = std::move(up);
-        // self-check: tiles cover the rows; every own free row is updated once,
-        // in its colour; every updated row's slots name its neighbours in order
-        if (P.tile_ptr.back() != n) fail(LMS_ERR_STATE, "multicolour plan: tiles do not cover the rows");
+        // self-check: tiles cover the rows (patches: every free row once);
+        // every own free row is updated once, in its colour; every updated
+        // row's slots name its neighbours in order
+        if (P.tile_ptr.back() != (patches ? M.n_free : n))
+            fail(LMS_ERR_STATE, "multicolour plan: tiles do not cover the rows");
+        std::vector<uint8_t> owned(patches ? size_t(n) : 0, 0);
         for (int32_t t = 0; t < P.tiles; ++t) {
             const int32_t b = P.tile_ptr[size_t(t)], e = P.tile_ptr[size_t(t) + 1], nown = e - b;
             const int64_t hb = P.halo_ptr[size_t(t)];
-            const int32_t nst = nown + int32_t(P.halo_ptr[size_t(t) + 1] - hb);
-            auto global_of = [&](int32_t sl) { return sl < nown ? b + sl : P.halo[size_t(hb + sl - nown)]; };
+            const int32_t nst = int32_t(P.halo_ptr[size_t(t) + 1] - hb) + (patches ? 0 : nown);
+            if (nown <= 0 || nst < nown) fail(LMS_ERR_STATE, "multicolour plan: tile counts");
+            auto global_of = [&](int32_t sl) {
+                if (patches) return P.halo[size_t(hb + sl)];
+                return sl < nown ? b + sl : P.halo[size_t(hb + sl - nown)];
+            };
+            if (patches)
+                for (int32_t sl = 0; sl < nown; ++sl) {
+                    const int32_t v = global_of(sl);
+                    if (v < 0 || v >= n || M.fixed[size_t(v)] || owned[size_t(v)] || (sl > 0 && v <= global_of(sl - 1)))
+                        fail(LMS_ERR_STATE, "multicolour plan: patch rows");
+                    owned[size_t(v)] = 1;
+                }
             std::vector<uint8_t> seen(size_t(nst), 0);
             for (int32_t c = 0; c < C; ++c)
                 for (int64_t i = P.upd_ptr[size_t(t) * size_t(C + 1) + size_t(c)];
@@ -1294,13 +1341,15 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap) {
                     }
                 }
             for (int32_t sl = 0; sl < nown; ++sl)
-                if (!M.fixed[size_t(b + sl)] && !seen[size_t(sl)]) fail(LMS_ERR_STATE, "multicolour plan: own row missed");
+                if (!M.fixed[size_t(global_of(sl))] && !seen[size_t(sl)])
+                    fail(LMS_ERR_STATE, "multicolour plan: own row missed");
         }
     } else {
         P = Mesh::MCPlan{};
         P.ts = ts;
         P.l_cap = l_cap;
         P.u_cap = u_cap;
+        P.patches = patches;
         P.fits = false;
     }
     P.version = M.version;

@@ -159,11 +159,12 @@ struct Mesh {
     // past the row's end, in the row's order).
     struct MCPlan {
         int32_t ts = 0, l_cap = 0, u_cap = 0;
+        bool patches = false;  // tiles are breadth-first patches of free rows (as for TBPlan)
         bool fits = true;
         int32_t tiles = 0, l_max = 0, colors = 0;
-        std::vector<int32_t> tile_ptr;  // tiles+1
+        std::vector<int32_t> tile_ptr;  // tiles+1 (patches: prefix of own counts)
         std::vector<int64_t> halo_ptr;  // tiles+1
-        std::vector<int32_t> halo;      // staged ids beyond the own rows
+        std::vector<int32_t> halo;      // staged ids beyond the own rows (patches: own rows first)
         std::vector<int64_t> upd_ptr;   // tiles*(C+1)
         std::vector<uint16_t> urow, uidx;
         // quality evaluated in the pass (as for TBPlan, slots into this
@@ -203,7 +204,8 @@ void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap, bool patches = false);
 void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
-const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap);
+const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, bool patches = false);
+const Mesh::Patches &patch_set(Mesh &M, int32_t ts);
 void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P);
 void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,
                    int32_t record_bytes, lms_reuse_stats &out);

@@ -901,7 +901,10 @@ __global__ __launch_bounds__(BS) void k_colour2(const int32_t *__restrict__ list
 // quality of the state it sweeps from over the tile's triangles (their
 // corners are all staged) into qpart[tile]; its depth (1, or 0 once all
 // sweeps are done: quality only) comes from the device state.
-template <typename T, int BS, int W, int R, int MAP, bool QUAL>
+//
+// G (patch tiles): the own rows are the first nown entries of the staged
+// list (halo_ptr/halo cover every staged row), read and written through it.
+template <typename T, int BS, int W, int R, int MAP, bool QUAL, bool G>
 __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__ tile_ptr,
                                                      const int64_t *__restrict__ halo_ptr,
                                                      const int32_t *__restrict__ halo,
@@ -927,7 +930,8 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
     const int tid = int(threadIdx.x);
     const int32_t b = tile_ptr[tile], nown = tile_ptr[tile + 1] - b;
     const int64_t hb = halo_ptr[tile];
-    const int32_t nh = int32_t(halo_ptr[tile + 1] - hb);
+    const int32_t nh = int32_t(halo_ptr[tile + 1] - hb);  // rows read through the list
+    const int32_t g0 = G ? 0 : nown;                      // slot of its first entry
     // this thread's updated rows (the tile's list, colour by colour): slot,
     // colour and neighbour slots, held in registers for the whole pass
     const int64_t *up = upd_ptr + int64_t(tile) * (C + 1);
@@ -946,7 +950,8 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
             colr[r] = c;
         }
     }
-    for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
+    if constexpr (!G)
+        for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
     for (int32_t j0 = tid; j0 < nh; j0 += 4 * BS) {
         int32_t g[4];
 #pragma unroll
@@ -968,7 +973,7 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
                 vec2_t<T> h;
                 h.x = hx[q];
                 h.y = hy[q];
-                sp[nown + j0 + q * BS] = h;
+                sp[g0 + j0 + q * BS] = h;
             }
     }
     __syncthreads();
@@ -1016,7 +1021,7 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
         }
         __syncthreads();
     }
-    for (int32_t i = tid; i < nown; i += BS) dst[b + i] = sp[i];
+    for (int32_t i = tid; i < nown; i += BS) dst[G ? halo[hb + i] : b + i] = sp[i];
 }
 
 // Quality (Section 3.2) of one triangle: shortest / longest Euclidean edge.
