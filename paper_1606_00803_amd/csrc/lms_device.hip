@@ -1494,7 +1494,10 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
     const int reps = M.n > (1 << 22) ? 3 : 8;
     float best = 3.0e38f;
     hipError_t err = hipSuccess;
+    // from 4M rows on, only patch variants are timed (as for the sweep tuner:
+    // patches won wherever both were measured, and every plan costs memory)
     for (int c = -1; c < kNumMcConfigs && err == hipSuccess; ++c) {
+        if (c >= 0 && M.n >= kDropPlansFrom && !mc_shape(c).g) continue;
         if (c >= 0 && !mc_usable<T>(d, M, c)) continue;
         auto one = [&]() {
             if (c < 0)
