@@ -792,29 +792,33 @@ vec2_t<T> *ensure_packed(DeviceState &d, int which, int32_t n) {
     return static_cast<vec2_t<T> *>(d.pk[pi][which]);
 }
 
-// One-pass multicolour variants: MC(id, tile size, staging cap, updated
-// rows per thread R (256 threads), map, patches).  patches = 1: tiles are
-// breadth-first patches of free rows, as for the temporally blocked sweep.
-#define LMS_MC_CONFIGS(MC)          \
-    MC(0, 128, 1024, 2, 16, 0)      \
-    MC(1, 128, 1024, 2, 0, 0)       \
-    MC(2, 256, 2048, 4, 16, 0)      \
-    MC(3, 64, 512, 1, 16, 0)        \
-    MC(4, 256, 1024, 2, 16, 1)      \
-    MC(5, 512, 2048, 4, 0, 1)       \
-    MC(6, 512, 2048, 4, 16, 1)      \
-    MC(7, 1024, 4096, 8, 0, 1)
-constexpr int kNumMcConfigs = 8;
+// One-pass multicolour variants: MC(id, block size, tile size, staging cap,
+// updated rows per thread R, map, patches).  A tile updates at most block
+// size x R rows.  patches = 1: tiles are breadth-first patches of free rows,
+// as for the temporally blocked sweep.
+#define LMS_MC_CONFIGS(MC)               \
+    MC(0, 256, 128, 1024, 2, 16, 0)      \
+    MC(1, 256, 128, 1024, 2, 0, 0)       \
+    MC(2, 256, 256, 2048, 4, 16, 0)      \
+    MC(3, 256, 64, 512, 1, 16, 0)        \
+    MC(4, 256, 256, 1024, 2, 16, 1)      \
+    MC(5, 256, 512, 2048, 4, 0, 1)       \
+    MC(6, 256, 512, 2048, 4, 16, 1)      \
+    MC(7, 256, 1024, 4096, 8, 0, 1)      \
+    MC(8, 512, 512, 2048, 2, 0, 1)       \
+    MC(9, 1024, 1024, 2048, 2, 0, 1)     \
+    MC(10, 1024, 2048, 4096, 4, 0, 1)
+constexpr int kNumMcConfigs = 11;
 
 struct MCShape {
-    int ts = 0, lcap = 0, r = 0, map = 0, g = 0;
+    int bs = 0, ts = 0, lcap = 0, r = 0, map = 0, g = 0;
 };
 
 MCShape mc_shape(int cfg) {
     switch (cfg) {
-#define MC(id, ts, lcap, r, map, g) \
-    case id:                        \
-        return MCShape{ts, lcap, r, map, g};
+#define MC(id, bs, ts, lcap, r, map, g) \
+    case id:                            \
+        return MCShape{bs, ts, lcap, r, map, g};
         LMS_MC_CONFIGS(MC)
 #undef MC
     }
@@ -824,7 +828,7 @@ MCShape mc_shape(int cfg) {
 // Whether a resident multicolour plan is the one of shape t.
 template <class P>
 bool mc_plan_is(const P &p, const MCShape &t) {
-    return p.ts == t.ts && p.l_cap == t.lcap && p.u_cap == 256 * t.r && p.patches == (t.g != 0);
+    return p.ts == t.ts && p.l_cap == t.lcap && p.u_cap == t.bs * t.r && p.patches == (t.g != 0);
 }
 
 // Meshes from this many rows on drop, after each tuning, the tile plans that
@@ -1382,7 +1386,7 @@ const DeviceState::MCDev &ensure_mc(DeviceState &d, Mesh &M, const MCShape &t) {
     for (const auto &h : d.mcs)
         if (mc_plan_is(h, t)) return h;
     const auto t0 = std::chrono::steady_clock::now();
-    const Mesh::MCPlan &P = mc_plan(M, t.ts, t.lcap, 256 * t.r, t.g != 0);
+    const Mesh::MCPlan &P = mc_plan(M, t.ts, t.lcap, t.bs * t.r, t.g != 0);
     if (env_flag("LMS_VERBOSE", false))
         std::fprintf(stderr, "[lms] multicolour plan %s ts=%d: %d tiles, %s, %.2f s\n", t.g ? "patches" : "ranges",
                      t.ts, P.tiles, P.fits ? "fits" : "does not fit",
@@ -1390,7 +1394,7 @@ const DeviceState::MCDev &ensure_mc(DeviceState &d, Mesh &M, const MCShape &t) {
     DeviceState::MCDev h;
     h.ts = t.ts;
     h.l_cap = t.lcap;
-    h.u_cap = 256 * t.r;
+    h.u_cap = t.bs * t.r;
     h.patches = t.g != 0;
     h.fits = P.fits;
     h.tiles = P.tiles;
@@ -1421,9 +1425,9 @@ bool mc_usable(DeviceState &d, Mesh &M, int cfg) {
 template <typename T, int W, class Go>
 void mc_dispatch(int cfg, Go &&go) {
     switch (cfg) {
-#define MC(id, ts, lcap, r, map, g)                                                                   \
-    case id:                                                                                          \
-        go(k_colour_tiles<T, 256, W, r, map, false, g != 0>, k_colour_tiles<T, 256, W, r, map, true, g != 0>); \
+#define MC(id, bs, ts, lcap, r, map, g)                                                             \
+    case id:                                                                                        \
+        go(bs, k_colour_tiles<T, bs, W, r, map, false, g != 0>, k_colour_tiles<T, bs, W, r, map, true, g != 0>); \
         break;
         LMS_MC_CONFIGS(MC)
 #undef MC
@@ -1444,13 +1448,13 @@ void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src,
     if (size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024) fail(LMS_ERR_STATE, "multicolour plan too large");
     if (qual && (!h->q_ready || !h->q_fits || !st)) fail(LMS_ERR_STATE, "quality-fused multicolour pass without its plan");
     const size_t lds = size_t(h->l_max) * sizeof(vec2_t<T>);
-    auto go = [&](auto plain, auto fused) {
+    auto go = [&](int bs, auto plain, auto fused) {
         if (qual)
-            fused<<<h->tiles, 256, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
-                                             h->colors, src, dst, st, h->qtri_ptr, h->qtri, h->qpart, max_iters);
+            fused<<<h->tiles, bs, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
+                                            h->colors, src, dst, st, h->qtri_ptr, h->qtri, h->qpart, max_iters);
         else
-            plain<<<h->tiles, 256, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
-                                             h->colors, src, dst, st, nullptr, nullptr, nullptr, 0);
+            plain<<<h->tiles, bs, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
+                                            h->colors, src, dst, st, nullptr, nullptr, nullptr, 0);
     };
     switch (M.ell_w) {
         case 8:

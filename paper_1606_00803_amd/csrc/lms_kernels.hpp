@@ -1087,15 +1087,20 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
 // where w_t = sum over the corners of 1/|T(v)| (the 1/|V| of the global mean
 // is applied by the final reduction).  Optionally stores q_t.  Each triangle
 // is one 16-byte record (corners a, b, c; counts |T(v)| packed 10 bits each,
-// from which w_t is recomputed in the same order as on the host); each thread
-// takes four triangles per step, loads first.
+// from which w_t is recomputed in the same order as on the host: 1/c from a
+// 64-entry table filled by the same division, beyond it divided); each
+// thread takes four triangles per step, loads first.
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_quality(const int32_t *__restrict__ trec, const T *__restrict__ x,
                                                 const T *__restrict__ y, const vec2_t<T> *__restrict__ xy,
                                                 int64_t ntri, double *__restrict__ partials,
                                                 double *__restrict__ qt_out, const StopState *__restrict__ st) {
     __shared__ double s_red[BS / 64];
+    __shared__ double s_rcp[65];
     if (st && st->done) return;
+    for (int c = int(threadIdx.x); c <= 64; c += BS) s_rcp[c] = c == 0 ? 0.0 : 1.0 / double(c);
+    __syncthreads();
+    auto rcp = [&](uint32_t c) { return c <= 64u ? s_rcp[c] : 1.0 / double(c); };
     double acc = 0.0;
     const int64_t stride = int64_t(gridDim.x) * BS;
     for (int64_t t0 = int64_t(blockIdx.x) * BS + threadIdx.x; t0 < ntri; t0 += 4 * stride) {
@@ -1111,8 +1116,7 @@ __global__ __launch_bounds__(BS) void k_quality(const int32_t *__restrict__ trec
             if (t < ntri) {
                 const double qt = tri_quality_at(x, y, xy, r[q].x, r[q].y, r[q].z);
                 const uint32_t cnt = uint32_t(r[q].w);
-                const double w = 1.0 / double(cnt & 1023u) + 1.0 / double((cnt >> 10) & 1023u) +
-                                 1.0 / double(cnt >> 20);
+                const double w = rcp(cnt & 1023u) + rcp((cnt >> 10) & 1023u) + rcp(cnt >> 20);
                 if (qt_out) qt_out[t] = qt;
                 acc += qt * w;
             }

@@ -728,7 +728,7 @@ def test_one_pass_multicolour_same_bits_as_colour_by_colour(prec, kind):
                                         check_quality=kw["check_quality"], **extra)
             os.environ.pop("LMS_COLOUR_TILES")
             ran = 0
-            for cfg in range(8):                     # 0-3 row ranges, 4-7 patches
+            for cfg in range(11):                    # 0-3 row ranges, 4-10 patches
                 os.environ["LMS_COLOUR_CONFIG"] = str(cfg)
                 try:
                     x, y, r, _ = run_library(m, kind, kw["max_iters"], dtype=dt, M=M, scheme="multicolor",
@@ -744,7 +744,7 @@ def test_one_pass_multicolour_same_bits_as_colour_by_colour(prec, kind):
                 for key in ("q0", "q_final", "last_dq"):         # fused quality vs the separate pass
                     a, b = r[key], rr[key]
                     assert (math.isnan(a) and math.isnan(b)) or abs(a - b) <= 1e-12, (cfg, kw, key)
-            assert ran >= 6, kind
+            assert ran >= 9, kind
             if prec == "f64" and not kw["check_quality"]:
                 ex, ey = osm.multicolor(top, cols[0], cols[1], m.x, m.y, kw["max_iters"])
                 assert np.max(np.abs(rx - ex)) <= TOL64 * extent(m.xy)
