@@ -234,10 +234,17 @@ def roofline_of(r, prec="f64", workload="ocean"):
     # bytes are k x B_sweep, over a launch that lasts k x the time per sweep
     k = sweeps_per_launch(r["sweep_kernel"])
     traffic = counters_traffic(r["sweep_kernel"], prec, COUNTERS[workload]) if workload in COUNTERS else None
-    return {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "sweep " + r["sweep_kernel"], "sweeps_per_launch": k,
-            "bytes_per_launch": k * r["bytes_per_sweep"], "avg_launch_us": k * r["sweep_us_events"]}
+    launch_us = k * r["sweep_us_events"]
+    out = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+           "kernel": "sweep " + r["sweep_kernel"], "sweeps_per_launch": k,
+           "bytes_per_launch": k * r["bytes_per_sweep"], "avg_launch_us": launch_us}
+    if traffic is not None and launch_us > 0:
+        # the bytes the launch really moves (counters) over its measured duration
+        out["traffic_gbs"] = traffic / (launch_us * 1e-6) / 1e9
+        out["traffic_frac"] = out["traffic_gbs"] / HBM_PEAK_GBS
+        out["traffic_per_algorithmic_byte"] = traffic / out["bytes_per_launch"]
+    return out
 
 
 def with_stream_copy(torch, roof):

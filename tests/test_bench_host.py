@@ -45,6 +45,19 @@ def test_roofline_scales_bytes_and_time_by_the_depth():
     roof = bench.roofline_of(r, "f64", "no-such-workload")
     assert roof["bytes_per_launch"] == 2000 and roof["avg_launch_us"] == 6.0
     assert roof["frac"] == pytest.approx(0.5) and roof["traffic"] is None and roof["bound"] == "hbm"
+    assert "traffic_gbs" not in roof
+
+
+def test_roofline_reports_the_physical_rate_when_counters_exist(tmp_path, monkeypatch):
+    name = "tb/ts256/k2/bs256/w8/r2/l1024/xcd16"
+    summary = tmp_path / "c.md"
+    summary.write_text(f"- source_sha256: {bench.device_source_hash()}\n\n| `{name}` | f64 | 1.0 / 2.0 | 600 | 0.3 |  |\n")
+    monkeypatch.setitem(bench.COUNTERS, "toy", str(summary))
+    r = dict(sweep_kernel=name, achieved_gbs=4000.0, bytes_per_sweep=1000, sweep_us_events=3.0)
+    roof = bench.roofline_of(r, "f64", "toy")
+    assert roof["traffic"] == 600.0
+    assert roof["traffic_gbs"] == pytest.approx(600 / 6e-6 / 1e9)      # 600 bytes in 2 x 3 us
+    assert roof["traffic_per_algorithmic_byte"] == pytest.approx(0.3)
 
 
 def test_counter_summary_is_used_only_for_the_current_source(tmp_path):
