@@ -152,6 +152,7 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
             M.smooth(x, y, tx, ty, scheme=scheme, max_iters=sweeps, check_quality=False)
             marks[i].record(t.s)
     per_step = [t.e0.elapsed_time(marks[0])] + [marks[i - 1].elapsed_time(marks[i]) for i in range(1, steps)]
+    launch_us = marginal_launch_us(torch, M, x, y, tx, ty, scheme) if scheme == "jacobi" else None
     info = M.info()
     s = 8 if prec == "f64" else 4
     b = sweep_bytes(info["n"], info["n_free"], info["nnz"], s)
@@ -164,8 +165,27 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
                achieved_gbs=b / (sweep_us * 1e-6) / 1e9,
                frac_hbm=b / (sweep_us * 1e-6) / 1e9 / HBM_PEAK_GBS, bytes_per_sweep=b,
                wall=t.wall, ev_ms=t.ms)
+    if launch_us is not None:
+        out["launch_us_marginal"] = launch_us
     del x0, y0, tx, ty
     return out, (x, y)
+
+
+def marginal_launch_us(torch, M, x, y, tx, ty, scheme, reps=5):
+    """Duration of one launch of the sweep kernel the handle runs for fixed K:
+    HIP events around `reps` calls of 2k and of 10k sweeps (k sweeps per
+    launch), the difference over the 8k extra sweeps, times k.  Pack, unpack
+    and the call's own overhead cancel; the gaps between launches stay."""
+    k = sweeps_per_launch(M.sweep_config("f64" if x.dtype == torch.float64 else "f32").split(" ")[0])
+    k1, k2 = 2 * k, 10 * k
+    ms = {}
+    for K in (k1, k2):
+        M.smooth(x, y, tx, ty, scheme=scheme, max_iters=K, check_quality=False)   # captures the graph
+        with Timer(torch) as t:
+            for _ in range(reps):
+                M.smooth(x, y, tx, ty, scheme=scheme, max_iters=K, check_quality=False)
+        ms[K] = t.ms
+    return (ms[k2] - ms[k1]) * 1e3 / (reps * (k2 - k1) / k)
 
 
 def cpu_baseline(m, sweeps, budget_s=10.0, one_core_s=3.0):
@@ -234,11 +254,16 @@ def roofline_of(r, prec="f64", workload="ocean"):
     # bytes are k x B_sweep, over a launch that lasts k x the time per sweep
     k = sweeps_per_launch(r["sweep_kernel"])
     traffic = counters_traffic(r["sweep_kernel"], prec, COUNTERS[workload]) if workload in COUNTERS else None
-    launch_us = k * r["sweep_us_events"]
-    out = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+    # the launch's own duration (marginal over fixed-K runs) when measured,
+    # else the whole call's time per launch (pack, unpack and overhead included)
+    launch_us = r.get("launch_us_marginal") or k * r["sweep_us_events"]
+    achieved = k * r["bytes_per_sweep"] / (launch_us * 1e-6) / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
            "kernel": "sweep " + r["sweep_kernel"], "sweeps_per_launch": k,
-           "bytes_per_launch": k * r["bytes_per_sweep"], "avg_launch_us": launch_us}
+           "bytes_per_launch": k * r["bytes_per_sweep"], "avg_launch_us": launch_us,
+           "avg_launch_us_whole_call": k * r["sweep_us_events"],
+           "launch_duration": "marginal" if r.get("launch_us_marginal") else "whole call"}
     if traffic is not None and launch_us > 0:
         # the bytes the launch really moves (counters) over its measured duration
         out["traffic_gbs"] = traffic / (launch_us * 1e-6) / 1e9

@@ -40,12 +40,16 @@ def test_sweeps_per_launch_reads_the_blocking_depth():
 
 
 def test_roofline_scales_bytes_and_time_by_the_depth():
-    r = dict(sweep_kernel="tb/ts256/k2/bs256/w8/r2/l1024/xcd16", achieved_gbs=4000.0,
-             bytes_per_sweep=1000, sweep_us_events=3.0)
+    r = dict(sweep_kernel="tb/ts256/k2/bs256/w8/r2/l1024/xcd16", bytes_per_sweep=12_000_000, sweep_us_events=3.0)
     roof = bench.roofline_of(r, "f64", "no-such-workload")
-    assert roof["bytes_per_launch"] == 2000 and roof["avg_launch_us"] == 6.0
+    assert roof["bytes_per_launch"] == 24_000_000 and roof["avg_launch_us"] == 6.0
+    assert roof["achieved"] == pytest.approx(4000.0)                 # 24 MB in 6 us
     assert roof["frac"] == pytest.approx(0.5) and roof["traffic"] is None and roof["bound"] == "hbm"
-    assert "traffic_gbs" not in roof
+    assert roof["launch_duration"] == "whole call" and "traffic_gbs" not in roof
+    # a measured marginal launch duration takes precedence over the call's time per launch
+    roof = bench.roofline_of(dict(r, launch_us_marginal=5.0), "f64", "no-such-workload")
+    assert roof["avg_launch_us"] == 5.0 and roof["avg_launch_us_whole_call"] == 6.0
+    assert roof["achieved"] == pytest.approx(4800.0) and roof["launch_duration"] == "marginal"
 
 
 def test_roofline_reports_the_physical_rate_when_counters_exist(tmp_path, monkeypatch):
@@ -53,7 +57,7 @@ def test_roofline_reports_the_physical_rate_when_counters_exist(tmp_path, monkey
     summary = tmp_path / "c.md"
     summary.write_text(f"- source_sha256: {bench.device_source_hash()}\n\n| `{name}` | f64 | 1.0 / 2.0 | 600 | 0.3 |  |\n")
     monkeypatch.setitem(bench.COUNTERS, "toy", str(summary))
-    r = dict(sweep_kernel=name, achieved_gbs=4000.0, bytes_per_sweep=1000, sweep_us_events=3.0)
+    r = dict(sweep_kernel=name, bytes_per_sweep=1000, sweep_us_events=3.0)
     roof = bench.roofline_of(r, "f64", "toy")
     assert roof["traffic"] == 600.0
     assert roof["traffic_gbs"] == pytest.approx(600 / 6e-6 / 1e9)      # 600 bytes in 2 x 3 us
