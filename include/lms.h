@@ -187,7 +187,13 @@ lms_status lms_permute(lms_mesh_t m, const void *sx, const void *sy, void *dx, v
  * between chunks of sweeps, so that path waits for the stream as it runs.
  * Calls on one handle from different streams are ordered by the handle (each
  * waits for the previous call); the caller orders its own reads and writes of
- * x, y (and tx, ty) with the stream. */
+ * x, y (and tx, ty) with the stream.
+ * The first call per precision after a reorder tunes on the caller's stream
+ * and waits for it: it times the sweep variants (and builds their tile plans
+ * on the host), the one-launch path of a batch of small meshes, the one-pass
+ * multicolour variants (LMS_MULTICOLOR), and, under the stopping rule, the
+ * quality-fused passes.  Make that call before capturing work into a graph of
+ * your own.  Every variant gives the same result bits. */
 lms_status lms_smooth(lms_mesh_t m, void *x, void *y, void *tx, void *ty,
                       lms_precision p, lms_scheme s, const lms_smooth_opts *o,
                       void *stream, lms_smooth_result *r);
