@@ -171,6 +171,24 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
     return out, (x, y)
 
 
+def fp32_vs_fp64(torch, M, m, sweeps, scheme="jacobi"):
+    """Position error of the float32 form against the float64 form on the same
+    GPU: both run `sweeps` sweeps from P_0 under the handle's ordering; the
+    max and RMS distance per vertex over the mesh extent."""
+    out = {}
+    for dt in (torch.float64, torch.float32):
+        x0 = torch.as_tensor(m.x, dtype=dt, device="cuda")
+        y0 = torch.as_tensor(m.y, dtype=dt, device="cuda")
+        x, y = torch.empty_like(x0), torch.empty_like(y0)
+        M.permute(x0, y0, x, y)
+        M.smooth(x, y, scheme=scheme, max_iters=sweeps, check_quality=False)
+        out[dt] = (x.double().cpu().numpy(), y.double().cpu().numpy())
+    ext = float(np.ptp(np.stack([m.x, m.y], axis=1), axis=0).max())
+    d = np.hypot(out[torch.float32][0] - out[torch.float64][0], out[torch.float32][1] - out[torch.float64][1]) / ext
+    return dict(max=float(d.max()), rms=float(np.sqrt(np.mean(d ** 2))), sweeps=sweeps,
+                normalised_by="mesh extent (largest bounding-box side)")
+
+
 def marginal_launch_us(torch, M, x, y, tx, ty, scheme, reps=5):
     """Duration of one launch of the sweep kernel the handle runs for fixed K:
     HIP events around `reps` calls of 2k and of 10k sweeps (k sweeps per
@@ -313,6 +331,9 @@ def bench_ocean(torch, args):
     extras = {}
     if not args.no_extras:
         M.reorder("rdr", x0=m.x, y0=m.y)
+        extras["fp32_vs_fp64_rdr"] = fp32_vs_fp64(torch, M, m, SWEEPS)
+        log(f"float32 against float64 after {SWEEPS} sweeps: max {extras['fp32_vs_fp64_rdr']['max']:.3e}, "
+            f"rms {extras['fp32_vs_fp64_rdr']['rms']:.3e} of extent")
         r, (x, y) = run_fixed(torch, M, m, "rdr", "f64", SWEEPS, args.steps, 1, scheme="multicolor")
         extras["multicolor_rdr_f64"] = {k: r[k] for k in ("vertex_updates_per_s", "sweep_us_events")}
         extras["multicolor_rdr_f64"]["colour_passes_per_sweep"] = info["n_colors"]
@@ -480,6 +501,9 @@ def bench_batch512(torch, args):
             results[f"{kind}_{prec}"] = r
             log(f"{kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  sweep "
                 f"{r['sweep_us_events']:8.2f} us  {r['achieved_gbs']:8.1f} GB/s  [{r['sweep_kernel']}]")
+    extras = {"fp32_vs_fp64_rdr": fp32_vs_fp64(torch, B, u, SWEEPS)}
+    log(f"float32 against float64 after {SWEEPS} sweeps: max {extras['fp32_vs_fp64_rdr']['max']:.3e}, "
+        f"rms {extras['fp32_vs_fp64_rdr']['rms']:.3e} of extent")
     # the same meshes split by size class, each class a batch of its own: the
     # class that fits in LDS (<= 4096 vertices) runs all sweeps in one launch
     # and may beat the per-sweep byte formula; the others run per sweep
@@ -500,7 +524,7 @@ def bench_batch512(torch, args):
                 f"{r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  {r['frac_hbm']:.2f} of the HBM peak "
                 f"by the per-sweep bytes  [{r['sweep_kernel']}]")
         del CB
-    extras = {"by_size_class_rdr": by_size}
+    extras["by_size_class_rdr"] = by_size
     # a batch of small meshes (every one fits in LDS): all sweeps in one launch,
     # against the per-sweep path
     small = meshgen.batch(count=8192, seed=44, n_min=256, n_max=2000)
