@@ -88,10 +88,12 @@ struct DeviceState {
     struct MCDev {
         int32_t ts = 0, l_cap = 0, u_cap = 0, tiles = 0, l_max = 0, colors = 0;
         bool patches = false;
+        int32_t k = 1;
         bool fits = false;
         int32_t *tile_ptr = nullptr, *halo = nullptr;
         int64_t *halo_ptr = nullptr, *upd_ptr = nullptr;
         uint16_t *urow = nullptr, *uidx = nullptr;
+        uint8_t *umask = nullptr;
         bool q_ready = false, q_fits = false;
         int64_t *qtri_ptr = nullptr;
         uint32_t *qtri = nullptr;
@@ -102,6 +104,7 @@ struct DeviceState {
     };
     std::deque<MCDev> mcs;       // uploaded one-pass multicolour plans of the current version
     int mc_cfg[2] = {-2, -2};    // one-pass multicolour variant per precision; -1 = colour by colour; -2 = not tuned
+    int mc1_cfg[2] = {-1, -1};   // the fastest of one sweep per pass (the stopping rule runs it)
     int small_cfg[2] = {-2, -2}; // batch of small meshes: 1 = all sweeps in one launch, 0 = per sweep; -2 = not decided
     float small_us[2] = {-1.f, -1.f};  // measured one-launch time per sweep (microseconds)
     bool small_used[2] = {false, false};  // the last fixed-K Jacobi call ran the one-launch path
@@ -230,6 +233,7 @@ DeviceState &ensure_device(Mesh &M) {
         d->tbs.clear();
         d->mcs.clear();
         d->mc_cfg[0] = d->mc_cfg[1] = -2;
+        d->mc1_cfg[0] = d->mc1_cfg[1] = -1;
         d->small_cfg[0] = d->small_cfg[1] = -2;
         d->small_us[0] = d->small_us[1] = -1.f;
         d->small_used[0] = d->small_used[1] = false;
@@ -793,32 +797,37 @@ vec2_t<T> *ensure_packed(DeviceState &d, int which, int32_t n) {
 }
 
 // One-pass multicolour variants: MC(id, block size, tile size, staging cap,
-// updated rows per thread R, map, patches).  A tile updates at most block
-// size x R rows.  patches = 1: tiles are breadth-first patches of free rows,
-// as for the temporally blocked sweep.
-#define LMS_MC_CONFIGS(MC)               \
-    MC(0, 256, 128, 1024, 2, 16, 0)      \
-    MC(1, 256, 128, 1024, 2, 0, 0)       \
-    MC(2, 256, 256, 2048, 4, 16, 0)      \
-    MC(3, 256, 64, 512, 1, 16, 0)        \
-    MC(4, 256, 256, 1024, 2, 16, 1)      \
-    MC(5, 256, 512, 2048, 4, 0, 1)       \
-    MC(6, 256, 512, 2048, 4, 16, 1)      \
-    MC(7, 256, 1024, 4096, 8, 0, 1)      \
-    MC(8, 512, 512, 2048, 2, 0, 1)       \
-    MC(9, 1024, 1024, 2048, 2, 0, 1)     \
-    MC(10, 1024, 2048, 4096, 4, 0, 1)
-constexpr int kNumMcConfigs = 11;
+// updated rows per thread R, map, patches, sweeps per pass k).  A tile
+// updates at most block size x R rows.  patches = 1: tiles are breadth-first
+// patches of free rows, as for the temporally blocked sweep.  k > 1: a pass
+// runs up to k multicolour sweeps in LDS.
+#define LMS_MC_CONFIGS(MC)                  \
+    MC(0, 256, 128, 1024, 2, 16, 0, 1)      \
+    MC(1, 256, 128, 1024, 2, 0, 0, 1)       \
+    MC(2, 256, 256, 2048, 4, 16, 0, 1)      \
+    MC(3, 256, 64, 512, 1, 16, 0, 1)        \
+    MC(4, 256, 256, 1024, 2, 16, 1, 1)      \
+    MC(5, 256, 512, 2048, 4, 0, 1, 1)       \
+    MC(6, 256, 512, 2048, 4, 16, 1, 1)      \
+    MC(7, 256, 1024, 4096, 8, 0, 1, 1)      \
+    MC(8, 512, 512, 2048, 2, 0, 1, 1)       \
+    MC(9, 1024, 1024, 2048, 2, 0, 1, 1)     \
+    MC(10, 1024, 2048, 4096, 4, 0, 1, 1)    \
+    MC(11, 256, 512, 2048, 4, 0, 1, 2)      \
+    MC(12, 256, 384, 2048, 4, 16, 1, 2)     \
+    MC(13, 512, 1024, 4096, 4, 0, 1, 2)     \
+    MC(14, 256, 256, 2048, 4, 16, 1, 3)
+constexpr int kNumMcConfigs = 15;
 
 struct MCShape {
-    int bs = 0, ts = 0, lcap = 0, r = 0, map = 0, g = 0;
+    int bs = 0, ts = 0, lcap = 0, r = 0, map = 0, g = 0, k = 1;
 };
 
 MCShape mc_shape(int cfg) {
     switch (cfg) {
-#define MC(id, bs, ts, lcap, r, map, g) \
-    case id:                            \
-        return MCShape{bs, ts, lcap, r, map, g};
+#define MC(id, bs, ts, lcap, r, map, g, k) \
+    case id:                               \
+        return MCShape{bs, ts, lcap, r, map, g, k};
         LMS_MC_CONFIGS(MC)
 #undef MC
     }
@@ -828,7 +837,7 @@ MCShape mc_shape(int cfg) {
 // Whether a resident multicolour plan is the one of shape t.
 template <class P>
 bool mc_plan_is(const P &p, const MCShape &t) {
-    return p.ts == t.ts && p.l_cap == t.lcap && p.u_cap == t.bs * t.r && p.patches == (t.g != 0);
+    return p.ts == t.ts && p.l_cap == t.lcap && p.u_cap == t.bs * t.r && p.patches == (t.g != 0) && p.k == t.k;
 }
 
 // Meshes from this many rows on drop, after each tuning, the tile plans that
@@ -891,7 +900,8 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
     // one-pass multicolour plans: keep the tuned precisions' choices
     auto keep_mc = [&](const auto &plan) {
         for (int pi = 0; pi < 2; ++pi)
-            if (d.mc_cfg[pi] >= 0 && mc_plan_is(plan, mc_shape(d.mc_cfg[pi]))) return true;
+            for (int c : {d.mc_cfg[pi], d.mc1_cfg[pi]})
+                if (c >= 0 && mc_plan_is(plan, mc_shape(c))) return true;
         return false;
     };
     for (auto it = d.mcs.begin(); it != d.mcs.end();) {
@@ -902,6 +912,7 @@ void drop_unused_plans(DeviceState &d, Mesh &M) {
         for (const void *p : {static_cast<const void *>(it->tile_ptr), static_cast<const void *>(it->halo),
                               static_cast<const void *>(it->halo_ptr), static_cast<const void *>(it->upd_ptr),
                               static_cast<const void *>(it->urow), static_cast<const void *>(it->uidx),
+                              static_cast<const void *>(it->umask),
                               static_cast<const void *>(it->qtri_ptr), static_cast<const void *>(it->qtri),
                               static_cast<const void *>(it->qpart), static_cast<const void *>(it->qpart2),
                               static_cast<const void *>(it->qc_ids), static_cast<const void *>(it->qc_w)})
@@ -1386,16 +1397,17 @@ const DeviceState::MCDev &ensure_mc(DeviceState &d, Mesh &M, const MCShape &t) {
     for (const auto &h : d.mcs)
         if (mc_plan_is(h, t)) return h;
     const auto t0 = std::chrono::steady_clock::now();
-    const Mesh::MCPlan &P = mc_plan(M, t.ts, t.lcap, t.bs * t.r, t.g != 0);
+    const Mesh::MCPlan &P = mc_plan(M, t.ts, t.lcap, t.bs * t.r, t.g != 0, t.k);
     if (env_flag("LMS_VERBOSE", false))
-        std::fprintf(stderr, "[lms] multicolour plan %s ts=%d: %d tiles, %s, %.2f s\n", t.g ? "patches" : "ranges",
-                     t.ts, P.tiles, P.fits ? "fits" : "does not fit",
+        std::fprintf(stderr, "[lms] multicolour plan %s ts=%d k=%d: %d tiles, %s, %.2f s\n",
+                     t.g ? "patches" : "ranges", t.ts, t.k, P.tiles, P.fits ? "fits" : "does not fit",
                      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     DeviceState::MCDev h;
     h.ts = t.ts;
     h.l_cap = t.lcap;
     h.u_cap = t.bs * t.r;
     h.patches = t.g != 0;
+    h.k = t.k;
     h.fits = P.fits;
     h.tiles = P.tiles;
     h.l_max = P.l_max;
@@ -1407,6 +1419,7 @@ const DeviceState::MCDev &ensure_mc(DeviceState &d, Mesh &M, const MCShape &t) {
         h.upd_ptr = upload(&d, P.upd_ptr);
         h.urow = upload(&d, P.urow);
         h.uidx = upload(&d, P.uidx);
+        h.umask = upload(&d, P.umask);
     }
     d.mcs.push_back(h);
     return d.mcs.back();
@@ -1425,9 +1438,10 @@ bool mc_usable(DeviceState &d, Mesh &M, int cfg) {
 template <typename T, int W, class Go>
 void mc_dispatch(int cfg, Go &&go) {
     switch (cfg) {
-#define MC(id, bs, ts, lcap, r, map, g)                                                             \
+#define MC(id, bs, ts, lcap, r, map, g, k)                                                          \
     case id:                                                                                        \
-        go(bs, k_colour_tiles<T, bs, W, r, map, false, g != 0>, k_colour_tiles<T, bs, W, r, map, true, g != 0>); \
+        go(bs, k_colour_tiles<T, bs, W, r, map, false, g != 0, k>,                                  \
+           k_colour_tiles<T, bs, W, r, map, true, g != 0, k>);                                      \
         break;
         LMS_MC_CONFIGS(MC)
 #undef MC
@@ -1436,10 +1450,11 @@ void mc_dispatch(int cfg, Go &&go) {
     }
 }
 
-// One multicolour sweep src -> dst in one pass of variant cfg.
+// One pass of variant cfg src -> dst: `depth` multicolour sweeps (the last
+// `depth` of its plan; under the stopping rule, with qual, one).
 template <typename T>
 void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst,
-                   const StopState *st, hipStream_t s, bool qual = false, int32_t max_iters = 0) {
+                   const StopState *st, hipStream_t s, bool qual = false, int32_t max_iters = 0, int32_t depth = 1) {
     const MCShape t = mc_shape(cfg);
     const DeviceState::MCDev *h = nullptr;
     for (const auto &x : d.mcs)
@@ -1448,13 +1463,15 @@ void launch_mc_cfg(int cfg, DeviceState &d, const Mesh &M, const vec2_t<T> *src,
     if (size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024) fail(LMS_ERR_STATE, "multicolour plan too large");
     if (qual && (!h->q_ready || !h->q_fits || !st)) fail(LMS_ERR_STATE, "quality-fused multicolour pass without its plan");
     const size_t lds = size_t(h->l_max) * sizeof(vec2_t<T>);
+    if (depth < 1 || depth > t.k) fail(LMS_ERR_STATE, "multicolour pass deeper than its plan");
     auto go = [&](int bs, auto plain, auto fused) {
         if (qual)
             fused<<<h->tiles, bs, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
-                                            h->colors, src, dst, st, h->qtri_ptr, h->qtri, h->qpart, max_iters);
+                                            h->umask, h->colors, 1, src, dst, st, h->qtri_ptr, h->qtri, h->qpart,
+                                            max_iters);
         else
             plain<<<h->tiles, bs, lds, s>>>(h->tile_ptr, h->halo_ptr, h->halo, h->upd_ptr, h->urow, h->uidx,
-                                            h->colors, src, dst, st, nullptr, nullptr, nullptr, 0);
+                                            h->umask, h->colors, depth, src, dst, st, nullptr, nullptr, nullptr, 0);
     };
     switch (M.ell_w) {
         case 8:
@@ -1479,13 +1496,13 @@ template <typename T>
 void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_t s) {
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (d.mc_cfg[pi] != -2) return;
-    d.mc_cfg[pi] = -1;
+    d.mc_cfg[pi] = d.mc1_cfg[pi] = -1;
     if (!env_flag("LMS_COLOUR_TILES", true) || M.ell_w == 0) return;
     if (const char *f = std::getenv("LMS_COLOUR_CONFIG")) {
         const int c = std::atoi(f);
         if (c < 0 || c >= kNumMcConfigs || !mc_usable<T>(d, M, c))
             fail(LMS_ERR_ARG, "LMS_COLOUR_CONFIG names a one-pass multicolour variant this mesh cannot use");
-        d.mc_cfg[pi] = c;
+        d.mc_cfg[pi] = d.mc1_cfg[pi] = c;  // a deeper variant runs passes of depth 1 under the stopping rule
         return;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1496,18 +1513,19 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
         HIP_CHECK(ce);
     }
     const int reps = M.n > (1 << 22) ? 3 : 8;
-    float best = 3.0e38f;
+    float best = 3.0e38f, best1 = 3.0e38f;  // per sweep: every variant, and one sweep per pass
     hipError_t err = hipSuccess;
     // from 4M rows on, only patch variants are timed (as for the sweep tuner:
     // patches won wherever both were measured, and every plan costs memory)
     for (int c = -1; c < kNumMcConfigs && err == hipSuccess; ++c) {
         if (c >= 0 && M.n >= kDropPlansFrom && !mc_shape(c).g) continue;
         if (c >= 0 && !mc_usable<T>(d, M, c)) continue;
+        const int kk = c < 0 ? 1 : mc_shape(c).k;  // sweeps per timed pass
         auto one = [&]() {
             if (c < 0)
                 launch_colour_sweep2<T>(d, M, A, nullptr, s);
             else
-                launch_mc_cfg<T>(c, d, M, A, B, nullptr, s);
+                launch_mc_cfg<T>(c, d, M, A, B, nullptr, s, false, 0, kk);
         };
         one();
         err = hipEventRecord(e0, s);
@@ -1516,13 +1534,20 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        ms /= float(kk);
         if (err == hipSuccess && ms < best) {
             best = ms;
             d.mc_cfg[pi] = c;
         }
+        if (err == hipSuccess && kk == 1 && ms < best1) {
+            best1 = ms;
+            d.mc1_cfg[pi] = c;
+        }
         if (env_flag("LMS_VERBOSE", false))
             std::fprintf(stderr, "[lms] multicolour %s: %.2f us per sweep\n",
-                         c < 0 ? "colour by colour" : ("one pass, variant " + std::to_string(c)).c_str(),
+                         c < 0 ? "colour by colour"
+                               : ("one pass, variant " + std::to_string(c) + " (" + std::to_string(kk) +
+                                  " sweeps per pass)").c_str(),
                          double(ms) * 1000.0 / reps);
     }
     (void)hipEventDestroy(e0);
@@ -1570,7 +1595,10 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     vec2_t<T> *A = ensure_packed<T>(d, 0, M.n);
     vec2_t<T> *B = ensure_packed<T>(d, 1, M.n);
     if (colour) tune_colour<T>(d, M, A, B, s);  // before the pack: it sweeps the working copies
-    const int mc = colour ? d.mc_cfg[pi] : -1;    // >= 0: multicolour in one pass per sweep, A/B ping-pong
+    // >= 0: multicolour in one-pass sweeps, A/B ping-pong (under the stopping
+    // rule the fastest of one sweep per pass)
+    const int mc = colour ? (o.check_quality ? d.mc1_cfg[pi] : d.mc_cfg[pi]) : -1;
+    const int mck = mc >= 0 ? mc_shape(mc).k : 1;  // sweeps per pass for fixed K
     const bool in_place = colour && mc < 0;
     const int nb = (M.n + 255) / 256;
     k_pack<T><<<nb, 256, 0, s>>>(x, y, A, in_place ? nullptr : B, M.n);
@@ -1611,6 +1639,23 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                                     left -= kk;
                                 }
                             });
+        iters = K;
+        in_b = passes % 2 == 1;
+        r.stopped_by = LMS_STOP_MAX_ITERS;
+        r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
+    } else if (!o.check_quality && mck > 1) {
+        // multicolour, passes of up to mck sweeps, ping-pong A/B
+        const int32_t K = o.max_iters;
+        const int32_t passes = (K + mck - 1) / mck;
+        if (K > 0)
+            run_maybe_graph(d, "mcp|" + base + "|" + std::to_string(K), s, [&](hipStream_t cs) {
+                int32_t left = K;
+                for (int32_t q = 0; q < passes; ++q) {
+                    const int32_t kk = std::min(left, mck);
+                    launch_mc_cfg<T>(mc, d, M, q % 2 == 0 ? A : B, q % 2 == 0 ? B : A, nullptr, cs, false, 0, kk);
+                    left -= kk;
+                }
+            });
         iters = K;
         in_b = passes % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;

@@ -1128,12 +1128,14 @@ void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P) {
     }
 }
 
-const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, bool patches) {
+const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, bool patches, int32_t k) {
     for (const auto &h : M.mc_plans)
-        if (h.ts == ts && h.l_cap == l_cap && h.u_cap == u_cap && h.patches == patches && h.version == M.version)
+        if (h.ts == ts && h.l_cap == l_cap && h.u_cap == u_cap && h.patches == patches && h.k == k &&
+            h.version == M.version)
             return h;
     if (M.ell_w <= 0) fail(LMS_ERR_STATE, "no padded adjacency for a multicolour tile plan");
-    if (ts <= 0 || l_cap < 1 || l_cap >= 0xFFFF || u_cap < 1) fail(LMS_ERR_ARG, "multicolour plan: bad tile size or cap");
+    if (ts <= 0 || l_cap < 1 || l_cap >= 0xFFFF || u_cap < 1 || k < 1 || k > 8)
+        fail(LMS_ERR_ARG, "multicolour plan: bad tile size, cap or depth");
     const int32_t n = M.n, W = M.ell_w, C = M.n_colors;
     static const Mesh::Patches no_patches{0, 0, std::vector<int64_t>(1, 0), {}};
     const Mesh::Patches &ps = patches ? patch_set(M, ts) : no_patches;
@@ -1143,6 +1145,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
         std::vector<int32_t> tile_end, halo, halo_n;
         std::vector<int64_t> ucount;  // per tile and colour
         std::vector<uint16_t> urow, uidx;
+        std::vector<uint8_t> umask;
         int32_t l_max = 0;
     };
     const int workers = host_threads(nominal);
@@ -1153,66 +1156,93 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
     parallel_runs(nominal, workers, [&](int w, int64_t first, int64_t last) {
         Part &out = parts[size_t(w)];
         SlotMap slots(size_t(l_cap) + size_t(W) + 1);
-        std::vector<int32_t> staged, upd, queue;
-        std::vector<uint8_t> in_upd_mark;  // parallel to staged: updated here
-        // Stage the own rows (ascending), the closure of updated rows, their
-        // neighbours; false when the staging area passes the cap.
+        std::vector<int32_t> staged, upd, queue, seeds;
+        std::vector<uint8_t> in_upd_mark;  // parallel to staged: bit t-1 set when updated in sweep t
+        // Stage the own rows (ascending), the rows each sweep of the pass
+        // updates, their neighbours; false when a cap is exceeded.  Sweep k
+        // (the last) updates U_k: the own free rows and, closed downwards,
+        // every lower-colour neighbour of an updated row (read at this
+        // sweep's value).  Sweep t-1 updates U_{t-1}: the higher-colour
+        // neighbours of U_t (U_t reads them at sweep t-1's value), closed
+        // downwards the same way.  A pass of depth d runs sweeps k-d+1..k.
         auto try_tile = [&](const int32_t *own, int32_t nown) {
             slots.clear();
             staged.clear();
             in_upd_mark.clear();
-            queue.clear();
+            seeds.clear();
             for (int32_t i = 0; i < nown; ++i) {
                 const int32_t v = own[i];
                 slots.insert(v, i);
                 staged.push_back(v);
-                in_upd_mark.push_back(M.fixed[size_t(v)] ? 0 : 1);
-                if (!M.fixed[size_t(v)]) queue.push_back(v);
+                in_upd_mark.push_back(0);
+                if (!M.fixed[size_t(v)]) seeds.push_back(v);
             }
             if (int64_t(staged.size()) > l_cap) return false;
-            for (size_t qi = 0; qi < queue.size(); ++qi) {
-                if (int64_t(queue.size()) > u_cap) return false;
-                const int32_t v = queue[qi];
-                const int32_t cv = M.color[size_t(v)];
-                for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
-                    const int32_t u = M.col[size_t(j)];
-                    int32_t su = slots.get(u);
-                    if (su < 0) {
-                        su = int32_t(staged.size());
-                        slots.insert(u, su);
-                        staged.push_back(u);
-                        in_upd_mark.push_back(0);
-                        if (int64_t(staged.size()) > l_cap) return false;
-                    }
-                    // u is read by v: v needs u's value of this sweep when u's
-                    // colour comes first, so u is updated here too
-                    if (!M.fixed[size_t(u)] && M.color[size_t(u)] < cv && !in_upd_mark[size_t(su)]) {
-                        in_upd_mark[size_t(su)] = 1;
-                        queue.push_back(u);
+            int64_t nupd = 0;  // rows updated in some sweep
+            auto stage = [&](int32_t u) {
+                int32_t su = slots.get(u);
+                if (su < 0) {
+                    su = int32_t(staged.size());
+                    slots.insert(u, su);
+                    staged.push_back(u);
+                    in_upd_mark.push_back(0);
+                }
+                return su;
+            };
+            for (int32_t t = k; t >= 1; --t) {
+                const uint8_t bit = uint8_t(1u << (t - 1));
+                queue.clear();
+                auto mark = [&](int32_t v, int32_t sv) {
+                    if (in_upd_mark[size_t(sv)] & bit) return;
+                    if (!in_upd_mark[size_t(sv)]) ++nupd;
+                    in_upd_mark[size_t(sv)] |= bit;
+                    queue.push_back(v);
+                };
+                for (int32_t v : seeds) mark(v, stage(v));
+                for (size_t qi = 0; qi < queue.size(); ++qi) {
+                    if (nupd > u_cap || int64_t(staged.size()) > l_cap) return false;
+                    const int32_t v = queue[qi];
+                    const int32_t cv = M.color[size_t(v)];
+                    for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                        const int32_t u = M.col[size_t(j)];
+                        const int32_t su = stage(u);
+                        // u is read by v at this sweep's value when its colour comes first
+                        if (!M.fixed[size_t(u)] && M.color[size_t(u)] < cv) mark(u, su);
                     }
                 }
+                if (nupd > u_cap || int64_t(staged.size()) > l_cap) return false;
+                // rows of higher colour that U_t reads, at the previous sweep's value
+                seeds.clear();
+                if (t > 1)
+                    for (int32_t v : queue)
+                        for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                            const int32_t u = M.col[size_t(j)];
+                            if (!M.fixed[size_t(u)] && M.color[size_t(u)] > M.color[size_t(v)]) seeds.push_back(u);
+                        }
             }
-            return int64_t(queue.size()) <= u_cap;
+            return nupd <= u_cap;
         };
         auto emit_tile = [&](const int32_t *own, int32_t nown) {
             // slots: own rows, then the others in ascending id
             std::vector<int32_t> others(staged.begin() + nown, staged.end());
             std::sort(others.begin(), others.end());
             for (size_t i = 0; i < others.size(); ++i) slots.set(others[i], nown + int32_t(i));
-            // updated rows by colour, ascending slot inside a colour
-            std::vector<std::vector<int32_t>> by_colour(size_t(std::max(C, 1)));
+            // updated rows by colour, ascending slot inside a colour, with
+            // the sweeps of the pass that update them
+            std::vector<std::vector<std::pair<int32_t, uint8_t>>> by_colour(size_t(std::max(C, 1)));
             for (size_t i = 0; i < staged.size(); ++i)
                 if (in_upd_mark[i]) {
                     const int32_t v = staged[i];
-                    by_colour[size_t(M.color[size_t(v)])].push_back(slots.get(v));
+                    by_colour[size_t(M.color[size_t(v)])].emplace_back(slots.get(v), in_upd_mark[i]);
                 }
             for (int32_t c = 0; c < C; ++c) {
                 auto &rows = by_colour[size_t(c)];
                 std::sort(rows.begin(), rows.end());
                 out.ucount.push_back(int64_t(rows.size()));
-                for (int32_t sl : rows) {
+                for (const auto &[sl, msk] : rows) {
                     const int32_t v = sl < nown ? own[sl] : others[size_t(sl - nown)];
                     out.urow.push_back(uint16_t(sl));
+                    out.umask.push_back(msk);
                     const size_t base = out.uidx.size();
                     out.uidx.resize(base + size_t(W), uint16_t(0xFFFF));
                     for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
@@ -1274,6 +1304,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
     P.l_cap = l_cap;
     P.u_cap = u_cap;
     P.patches = patches;
+    P.k = k;
     P.colors = C;
     for (const auto &q : parts) P.fits = P.fits && q.fits;
     if (P.fits) {
@@ -1290,6 +1321,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
             P.halo.insert(P.halo.end(), q.halo.begin(), q.halo.end());
             P.urow.insert(P.urow.end(), q.urow.begin(), q.urow.end());
             P.uidx.insert(P.uidx.end(), q.uidx.begin(), q.uidx.end());
+            P.umask.insert(P.umask.end(), q.umask.begin(), q.umask.end());
             q = Part{};
         }
         P.tiles = int32_t(P.tile_ptr.size() - 1);
@@ -1320,13 +1352,20 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
                         fail(LMS_ERR_STATE, "multicolour plan: patch rows");
                     owned[size_t(v)] = 1;
                 }
-            std::vector<uint8_t> seen(size_t(nst), 0);
+            std::vector<uint8_t> seen(size_t(nst), 0);  // sweep mask of each updated slot
+            for (int64_t i = P.upd_ptr[size_t(t) * size_t(C + 1)]; i < P.upd_ptr[size_t(t) * size_t(C + 1) + size_t(C)];
+                 ++i) {
+                const int32_t sl = P.urow[size_t(i)];
+                const uint8_t msk = P.umask[size_t(i)];
+                if (sl >= nst || seen[size_t(sl)] || msk == 0 || (k < 8 && (msk >> k) != 0))
+                    fail(LMS_ERR_STATE, "multicolour plan: bad updated row");
+                seen[size_t(sl)] = msk;
+            }
             for (int32_t c = 0; c < C; ++c)
                 for (int64_t i = P.upd_ptr[size_t(t) * size_t(C + 1) + size_t(c)];
                      i < P.upd_ptr[size_t(t) * size_t(C + 1) + size_t(c) + 1]; ++i) {
                     const int32_t sl = P.urow[size_t(i)];
-                    if (sl >= nst || seen[size_t(sl)]) fail(LMS_ERR_STATE, "multicolour plan: bad updated row");
-                    seen[size_t(sl)] = 1;
+                    const uint8_t msk = P.umask[size_t(i)];
                     const int32_t v = global_of(sl);
                     if (M.fixed[size_t(v)] || M.color[size_t(v)] != c) fail(LMS_ERR_STATE, "multicolour plan: colour");
                     const int32_t deg = M.row_ptr[v + 1] - M.row_ptr[v];
@@ -1338,10 +1377,23 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
                         }
                         if (su >= nst || global_of(su) != M.col[size_t(M.row_ptr[v] + q)])
                             fail(LMS_ERR_STATE, "multicolour plan: slot names the wrong vertex");
+                        // in every sweep t it runs in, v reads a free lower-colour
+                        // neighbour at sweep t's value and a higher-colour one at
+                        // sweep t-1's (the staged value when t is the pass's first)
+                        const int32_t u = M.col[size_t(M.row_ptr[v] + q)];
+                        if (M.fixed[size_t(u)]) continue;
+                        const uint8_t mu = seen[size_t(su)];
+                        for (int32_t tt = 1; tt <= k; ++tt) {
+                            if (!((msk >> (tt - 1)) & 1u)) continue;
+                            if (M.color[size_t(u)] < c && !((mu >> (tt - 1)) & 1u))
+                                fail(LMS_ERR_STATE, "multicolour plan: lower-colour neighbour not updated");
+                            if (M.color[size_t(u)] > c && tt > 1 && !((mu >> (tt - 2)) & 1u))
+                                fail(LMS_ERR_STATE, "multicolour plan: higher-colour neighbour not updated");
+                        }
                     }
                 }
             for (int32_t sl = 0; sl < nown; ++sl)
-                if (!M.fixed[size_t(global_of(sl))] && !seen[size_t(sl)])
+                if (!M.fixed[size_t(global_of(sl))] && !((seen[size_t(sl)] >> (k - 1)) & 1u))
                     fail(LMS_ERR_STATE, "multicolour plan: own row missed");
         }
     } else {
@@ -1350,6 +1402,7 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
         P.l_cap = l_cap;
         P.u_cap = u_cap;
         P.patches = patches;
+        P.k = k;
         P.fits = false;
     }
     P.version = M.version;

@@ -160,6 +160,7 @@ struct Mesh {
     struct MCPlan {
         int32_t ts = 0, l_cap = 0, u_cap = 0;
         bool patches = false;  // tiles are breadth-first patches of free rows (as for TBPlan)
+        int32_t k = 1;         // multicolour sweeps per pass (a pass of depth d runs the last d)
         bool fits = true;
         int32_t tiles = 0, l_max = 0, colors = 0;
         std::vector<int32_t> tile_ptr;  // tiles+1 (patches: prefix of own counts)
@@ -167,6 +168,7 @@ struct Mesh {
         std::vector<int32_t> halo;      // staged ids beyond the own rows (patches: own rows first)
         std::vector<int64_t> upd_ptr;   // tiles*(C+1)
         std::vector<uint16_t> urow, uidx;
+        std::vector<uint8_t> umask;     // per updated row: bit t-1 set when sweep t of the pass updates it
         // quality evaluated in the pass (as for TBPlan, slots into this
         // plan's staging area); filled by mc_quality_plan
         bool q_built = false, q_fits = false;
@@ -204,7 +206,8 @@ void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std
 const Mesh::HaloPlan &halo_plan(Mesh &M, int32_t ts);
 const Mesh::TBPlan &tb_plan(Mesh &M, int32_t ts, int32_t k, int32_t u_cap, int32_t l_cap, bool patches = false);
 void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P);
-const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, bool patches = false);
+const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, bool patches = false,
+                            int32_t k = 1);
 const Mesh::Patches &patch_set(Mesh &M, int32_t ts);
 void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P);
 void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,

@@ -904,24 +904,31 @@ __global__ __launch_bounds__(BS) void k_colour2(const int32_t *__restrict__ list
 //
 // G (patch tiles): the own rows are the first nown entries of the staged
 // list (halo_ptr/halo cover every staged row), read and written through it.
-template <typename T, int BS, int W, int R, int MAP, bool QUAL, bool G>
+//
+// KP > 1 (several sweeps per pass): sweep t of the plan (t = 1..KP) updates
+// the rows whose mask has bit t-1: the last sweep the own free rows and the
+// lower-colour rows they read at its value; each earlier sweep the
+// higher-colour rows the next one reads at the previous value, closed the same
+// way.  A pass of depth d runs sweeps KP-d+1..KP, in LDS, colour by colour.
+template <typename T, int BS, int W, int R, int MAP, bool QUAL, bool G, int KP>
 __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__ tile_ptr,
                                                      const int64_t *__restrict__ halo_ptr,
                                                      const int32_t *__restrict__ halo,
                                                      const int64_t *__restrict__ upd_ptr,
                                                      const uint16_t *__restrict__ urow,
-                                                     const uint16_t *__restrict__ uidx, int32_t C,
+                                                     const uint16_t *__restrict__ uidx,
+                                                     const uint8_t *__restrict__ umask, int32_t C, int32_t depth,
                                                      const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst,
                                                      const StopState *__restrict__ st,
                                                      const int64_t *__restrict__ qtri_ptr,
                                                      const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
                                                      int32_t max_iters) {
+    static_assert(KP >= 1 && KP <= 8, "sweeps per pass");
     extern __shared__ unsigned char lds_raw[];
     __shared__ double s_red[BS / 64];
     __shared__ double s_rcp[QUAL ? 65 : 1];
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
     if (st && st->done) return;
-    int32_t depth = 1;
     if constexpr (QUAL) {
         depth = min(1, max_iters - st->swept);
         for (int c = int(threadIdx.x); c <= 64; c += BS) s_rcp[c] = c == 0 ? 0.0 : 1.0 / double(c);
@@ -937,14 +944,17 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
     const int64_t *up = upd_ptr + int64_t(tile) * (C + 1);
     uint32_t wd[R][W / 2];
     int32_t row[R], colr[R];
+    uint32_t msk[KP > 1 ? R : 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t e = up[0] + tid + BS * r;
         colr[r] = -1;
         row[r] = 0;
+        if constexpr (KP > 1) msk[r] = 0u;
         if (e < up[C]) {
             load_slot_words<W>(uidx + e * W, wd[r]);
             row[r] = urow[e];
+            if constexpr (KP > 1) msk[r] = umask[e];
             int32_t c = 0;
             while (up[c + 1] <= e) ++c;
             colr[r] = c;
@@ -996,30 +1006,34 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
         if (depth == 0) return;  // all sweeps done: the state was evaluated only
         __syncthreads();
     }
-    for (int32_t c = 0; c < C; ++c) {
+    for (int32_t t = KP - depth + 1; t <= KP; ++t) {
+        for (int32_t c = 0; c < C; ++c) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (colr[r] != c) continue;
-            T ax = T(0), ay = T(0);
-            int cnt = 0;
+            for (int r = 0; r < R; ++r) {
+                if (colr[r] != c) continue;
+                if constexpr (KP > 1)
+                    if (!((msk[r] >> (t - 1)) & 1u)) continue;
+                T ax = T(0), ay = T(0);
+                int cnt = 0;
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                const uint32_t id = (wd[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
-                if (id != 0xFFFFu) {
-                    const vec2_t<T> p = sp[id];
-                    ax += p.x;
-                    ay += p.y;
-                    ++cnt;
+                for (int q = 0; q < W; ++q) {
+                    const uint32_t id = (wd[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
+                    if (id != 0xFFFFu) {
+                        const vec2_t<T> p = sp[id];
+                        ax += p.x;
+                        ay += p.y;
+                        ++cnt;
+                    }
+                }
+                if (cnt > 0) {
+                    vec2_t<T> o;
+                    o.x = ax / T(cnt);
+                    o.y = ay / T(cnt);
+                    sp[row[r]] = o;
                 }
             }
-            if (cnt > 0) {
-                vec2_t<T> o;
-                o.x = ax / T(cnt);
-                o.y = ay / T(cnt);
-                sp[row[r]] = o;
-            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     for (int32_t i = tid; i < nown; i += BS) dst[G ? halo[hb + i] : b + i] = sp[i];
 }
