@@ -158,7 +158,7 @@ def run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup, scheme="jacobi"):
     b = sweep_bytes(info["n"], info["n_free"], info["nnz"], s)
     launches = steps * sweeps
     sweep_us = t.ms * 1e3 / launches
-    out = dict(sweep_kernel=M.sweep_config(prec).split(" ")[0] if scheme == "jacobi" else "colour",
+    out = dict(sweep_kernel=sweep_variant(M.sweep_config(prec), scheme),
                vertex_updates_per_s=info["n_free"] * launches / t.wall,
                ms_per_step=t.wall * 1e3 / steps, sweep_us_events=sweep_us,
                step_ms_median=float(np.median(per_step)), step_ms_min=float(min(per_step)),
@@ -261,6 +261,15 @@ def result_line(value, steps, warmup, ms_per_step, dtype, config, roofline, cpu,
     return out
 
 
+def sweep_variant(config, scheme="jacobi"):
+    """The variant a fixed-K call ran, from the library's sweep_config string:
+    its first name for Jacobi, the "colour=" one for multicolour."""
+    if scheme == "jacobi":
+        return config.split(" ")[0]
+    m = re.search(r"(?:^| )colour=(\S+)", config)
+    return m.group(1) if m else "colour"
+
+
 def sweeps_per_launch(kernel_name):
     """A temporally blocked variant ("tb/.../k2/...") runs k sweeps per launch."""
     m = re.search(r"^tb/.*?/k(\d+)/", kernel_name)
@@ -335,8 +344,8 @@ def bench_ocean(torch, args):
         log(f"float32 against float64 after {SWEEPS} sweeps: max {extras['fp32_vs_fp64_rdr']['max']:.3e}, "
             f"rms {extras['fp32_vs_fp64_rdr']['rms']:.3e} of extent")
         r, (x, y) = run_fixed(torch, M, m, "rdr", "f64", SWEEPS, args.steps, 1, scheme="multicolor")
-        extras["multicolor_rdr_f64"] = {k: r[k] for k in ("vertex_updates_per_s", "sweep_us_events")}
-        extras["multicolor_rdr_f64"]["colour_passes_per_sweep"] = info["n_colors"]
+        extras["multicolor_rdr_f64"] = {k: r[k] for k in ("vertex_updates_per_s", "sweep_us_events", "sweep_kernel")}
+        extras["multicolor_rdr_f64"]["colours"] = info["n_colors"]
         M.quality(x, y)
         with Timer(torch) as t:
             for _ in range(args.steps):

@@ -231,6 +231,10 @@ lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_p
  * kernel against the tuned per-sweep path and keeps the faster.  Once the
  * stopping rule has run with the quality fused into temporally blocked
  * passes, " stop=<variant>" names the variant it timed fastest in that form.
+ * Once LMS_MULTICOLOR has run, " colour=<variant>" names the multicolour
+ * variant of a fixed K ("by-colour": one launch per colour; "mc/...": all
+ * colours of k sweeps in one pass), followed by " colour_stop=<variant>" when
+ * the stopping rule runs another (it needs passes of one sweep).
  * buf: host
  * char[len] out, NUL-terminated, truncated to len-1 characters. */
 lms_status lms_sweep_config(lms_mesh_t m, lms_precision p, char *buf, int32_t len);

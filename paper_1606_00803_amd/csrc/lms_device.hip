@@ -834,6 +834,16 @@ MCShape mc_shape(int cfg) {
     return MCShape{};
 }
 
+// Name of a multicolour variant as lms_sweep_config reports it.
+std::string mc_config_name(int cfg) {
+    if (cfg < 0) return "by-colour";
+    const MCShape t = mc_shape(cfg);
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "mc/ts%d/k%d/bs%d/r%d/l%d/%s%s", t.ts, t.k, t.bs, t.r, t.lcap,
+                  map_name(t.map).c_str(), t.g ? "/patch" : "");
+    return buf;
+}
+
 // Whether a resident multicolour plan is the one of shape t.
 template <class P>
 bool mc_plan_is(const P &p, const MCShape &t) {
@@ -1980,19 +1990,25 @@ std::string dev_sweep_config(Mesh &M, lms_precision p) {
     const int pi = p == LMS_FP64 ? 0 : 1;
     const int c = M.dev->smooth_cfg[pi];
     // a batch of small meshes that runs all sweeps in one launch names that first
-    std::string small;
-    if (M.dev->small_used[pi]) small = "small/r" + std::to_string(small_batch_rows(M)) + "/one-launch";
-    if (c < 0) return small;
+    std::string out;
+    if (M.dev->small_used[pi]) out = "small/r" + std::to_string(small_batch_rows(M)) + "/one-launch";
+    auto add = [&out](const std::string &w) { out += (out.empty() ? "" : " ") + w; };
     // then the variant a fixed-K Jacobi lms_smooth runs, then the one it runs
     // under the stopping rule
-    std::string out = M.dev->tb_cfg[pi] >= 0 ? sweep_config_name(M.dev->tb_cfg[pi]) + " " + sweep_config_name(c)
-                                             : sweep_config_name(c);
-    if (!small.empty()) out = small + " " + out;
-    if (M.dev->tbq_cfg[pi] >= 0) out += " stop=" + sweep_config_name(M.dev->tbq_cfg[pi]);
+    if (c >= 0) {
+        if (M.dev->tb_cfg[pi] >= 0) add(sweep_config_name(M.dev->tb_cfg[pi]));
+        add(sweep_config_name(c));
+        if (M.dev->tbq_cfg[pi] >= 0) add("stop=" + sweep_config_name(M.dev->tbq_cfg[pi]));
+    }
+    // the multicolour variant of a fixed K, and the one of the stopping rule if another
+    if (M.dev->mc_cfg[pi] != -2) {
+        add("colour=" + mc_config_name(M.dev->mc_cfg[pi]));
+        if (M.dev->mc1_cfg[pi] != M.dev->mc_cfg[pi]) add("colour_stop=" + mc_config_name(M.dev->mc1_cfg[pi]));
+    }
+    if (c < 0) return out;
     char buf[64];
     for (int i = 0; i < kNumAllConfigs; ++i) {
-        std::snprintf(buf, sizeof(buf), "%s%d:%.2fus", i == 0 ? " tuned[" : " ", i,
-                      double(M.dev->tune_us[p == LMS_FP64 ? 0 : 1][i]));
+        std::snprintf(buf, sizeof(buf), "%s%d:%.2fus", i == 0 ? " tuned[" : " ", i, double(M.dev->tune_us[pi][i]));
         out += buf;
     }
     return out + "]";

@@ -39,6 +39,16 @@ def test_sweeps_per_launch_reads_the_blocking_depth():
     assert bench.sweeps_per_launch("ell2/bs128/w8/r2/linear") == 1
 
 
+def test_sweep_variant_reads_the_scheme_s_name():
+    cfg = ("tb/ts1024/k4/bs1024/w8/r2/l2048/xcd16/patch halo/ts256/w8/xcd stop=tb/ts512/k2/bs512/w8/r2/l1024/linear"
+           " colour=mc/ts1024/k2/bs512/r4/l4096/linear/patch colour_stop=mc/ts512/k1/bs256/r4/l2048/xcd16/patch"
+           " tuned[0:1.00us 1:2.00us]")
+    assert bench.sweep_variant(cfg) == "tb/ts1024/k4/bs1024/w8/r2/l2048/xcd16/patch"
+    assert bench.sweep_variant(cfg, "multicolor") == "mc/ts1024/k2/bs512/r4/l4096/linear/patch"
+    assert bench.sweep_variant("halo/ts256/w8/xcd colour=by-colour tuned[]", "multicolor") == "by-colour"
+    assert bench.sweep_variant("", "multicolor") == "colour"
+
+
 def test_roofline_scales_bytes_and_time_by_the_depth():
     r = dict(sweep_kernel="tb/ts256/k2/bs256/w8/r2/l1024/xcd16", bytes_per_sweep=12_000_000, sweep_us_events=3.0)
     roof = bench.roofline_of(r, "f64", "no-such-workload")

@@ -729,6 +729,7 @@ def test_one_pass_multicolour_same_bits_as_colour_by_colour(prec, kind):
             rx, ry, rr, _ = run_library(m, kind, kw["max_iters"], dtype=dt, M=M, scheme="multicolor",
                                         check_quality=kw["check_quality"], **extra)
             os.environ.pop("LMS_COLOUR_TILES")
+            assert "colour=by-colour" in M.sweep_config(prec).split(" ")
             ran = 0
             for cfg in range(15):                    # 0-3 row ranges, 4-10 patches, 11-14 several sweeps per pass
                 os.environ["LMS_COLOUR_CONFIG"] = str(cfg)
@@ -741,6 +742,9 @@ def test_one_pass_multicolour_same_bits_as_colour_by_colour(prec, kind):
                 finally:
                     os.environ.pop("LMS_COLOUR_CONFIG", None)
                 ran += 1
+                names = M.sweep_config(prec).split(" ")
+                assert any(w.startswith("colour=mc/ts") for w in names), (cfg, names)
+                assert not any(w.startswith("colour_stop=") for w in names), (cfg, names)
                 assert r["iters"] == rr["iters"] and r["stopped_by"] == rr["stopped_by"], (cfg, kw)
                 assert np.array_equal(x, rx) and np.array_equal(y, ry), (cfg, kw)
                 for key in ("q0", "q_final", "last_dq"):         # fused quality vs the separate pass
