@@ -579,6 +579,45 @@ def test_calls_on_two_streams_are_ordered_by_the_handle():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["jacobi", "multicolor"])
+def test_repeated_fixed_k_calls_on_the_same_arrays(prec, scheme):
+    # a fixed-K call on the arrays of the previous call runs the pack, the
+    # passes and the unpack as one graph: every replay, with eager work and
+    # synchronisation between replays, equals the call on fresh arrays, and K
+    # more sweeps on its result equal 2K sweeps from the start
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    dt = torch.float64 if prec == "f64" else torch.float32
+    m = meshgen.jittered_grid(300, seed=43, land_fraction=0.3)
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    M.reorder("rdr", x0=m.x, y0=m.y)
+    x0 = to_dev(m.x, dt)
+    y0 = to_dev(m.y, dt)
+
+    def fresh():
+        x = torch.empty_like(x0)
+        y = torch.empty_like(y0)
+        M.permute(x0, y0, x, y)
+        return x, y
+
+    x, y = fresh()
+    for K in (13, 9, 1):                         # odd and even pass counts at depths 1-4
+        rx, ry = fresh()
+        M.smooth(rx, ry, max_iters=K, check_quality=False, scheme=scheme)
+        r2x, r2y = fresh()
+        M.smooth(r2x, r2y, max_iters=2 * K, check_quality=False, scheme=scheme)
+        torch.cuda.synchronize()
+        for rep in range(4):                     # the first on other arrays than the last call's
+            M.permute(x0, y0, x, y)
+            M.smooth(x, y, max_iters=K, check_quality=False, scheme=scheme)
+            torch.cuda.synchronize()
+            assert torch.equal(x, rx) and torch.equal(y, ry), (K, rep)
+        M.smooth(x, y, max_iters=K, check_quality=False, scheme=scheme)
+        torch.cuda.synchronize()
+        assert torch.equal(x, r2x) and torch.equal(y, r2y), K
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("cfg", [45, 51, 54, 64, 67])  # width 8, depths 2, 3, 4; ranges and patches
 def test_fused_quality_stopping_rule_matches_separate_passes(prec, cfg):
     # the stopping rule with the quality evaluated inside the temporally
