@@ -105,6 +105,7 @@ struct DeviceState {
     std::deque<MCDev> mcs;       // uploaded one-pass multicolour plans of the current version
     int mc_cfg[2] = {-2, -2};    // one-pass multicolour variant per precision; -1 = colour by colour; -2 = not tuned
     int mc1_cfg[2] = {-1, -1};   // the fastest of one sweep per pass (the stopping rule runs it)
+    float mc_us[2] = {-1.f, -1.f};  // mc_cfg's measured time per sweep (microseconds; -1 = not timed)
     int small_cfg[2] = {-2, -2}; // batch of small meshes: 1 = all sweeps in one launch, 0 = per sweep; -2 = not decided
     float small_us[2] = {-1.f, -1.f};  // measured one-launch time per sweep (microseconds)
     bool small_used[2] = {false, false};  // the last fixed-K Jacobi call ran the one-launch path
@@ -131,7 +132,7 @@ struct DeviceState {
     std::vector<GraphEntry> graphs;
     bool use_graphs = true;
     // x, y of the last fixed-K packed lms_smooth: a call on the same arrays
-    // captures the pack and the unpack into the sweeps' graph
+    // issues the pack and the unpack with the passes (in their graph, if any)
     const void *io_x = nullptr, *io_y = nullptr;
     int sweep_cfg[2] = {-1, -1};     // separate-array sweep variant per precision, -1 = not tuned
     int smooth_cfg[2] = {-1, -1};    // variant lms_smooth uses (may sweep the interleaved copy)
@@ -1114,9 +1115,15 @@ void launch_stop(const DeviceState &d, const Mesh &M, int init, const lms_smooth
 
 // Run `body(stream)` either directly on `s`, or captured once into a graph
 // (cached under `key`) that is then launched on `s`.
+// A fixed-K call whose launches each run at least this long is issued launch
+// by launch: the host stays ahead of the device, and the end of a graph costs
+// more (about 8 us per call, measured on the 708k-vertex mesh) than the
+// launches it saves.
+constexpr float kDirectLaunchUs = 10.f;
+
 template <class F>
-void run_maybe_graph(DeviceState &d, const std::string &key, hipStream_t s, F body) {
-    if (!d.use_graphs) {
+void run_maybe_graph(DeviceState &d, const std::string &key, hipStream_t s, F body, bool direct = false) {
+    if (!d.use_graphs || direct) {
         body(s);
         launch_check();
         return;
@@ -1510,6 +1517,7 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (d.mc_cfg[pi] != -2) return;
     d.mc_cfg[pi] = d.mc1_cfg[pi] = -1;
+    d.mc_us[pi] = -1.f;
     if (!env_flag("LMS_COLOUR_TILES", true) || M.ell_w == 0) return;
     if (const char *f = std::getenv("LMS_COLOUR_CONFIG")) {
         const int c = std::atoi(f);
@@ -1551,6 +1559,7 @@ void tune_colour(DeviceState &d, Mesh &M, vec2_t<T> *A, vec2_t<T> *B, hipStream_
         if (err == hipSuccess && ms < best) {
             best = ms;
             d.mc_cfg[pi] = c;
+            d.mc_us[pi] = ms * 1000.f / float(reps);
         }
         if (err == hipSuccess && kk == 1 && ms < best1) {
             best1 = ms;
@@ -1615,10 +1624,11 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     const bool in_place = colour && mc < 0;
     const int nb = (M.n + 255) / 256;
     const int small_rows = colour || o.check_quality ? 0 : small;
-    // A fixed-K call on the same x, y as the previous one runs the pack, the
-    // passes and the unpack as one graph (keyed by x and y), which removes the
-    // launch gaps around the passes; other calls pack and unpack around it,
-    // so arrays that change from call to call capture no new graph.
+    // A fixed-K call on the same x, y as the previous one issues the pack and
+    // the unpack with the passes, in one graph keyed by x and y (or launch by
+    // launch when the launches are long), which removes the gaps around them;
+    // other calls pack and unpack around the passes, so arrays that change
+    // from call to call capture no new graph.
     const bool fixed_k = !o.check_quality && o.max_iters > 0 && small_rows == 0;
     const bool io_in_graph = fixed_k && d.io_x == x && d.io_y == y;
     if (fixed_k) {
@@ -1657,6 +1667,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         // temporally blocked: passes of up to `depth` sweeps, ping-pong A/B
         const int32_t K = o.max_iters, depth = sweep_config_depth(tb);
         const int32_t passes = (K + depth - 1) / depth;
+        const bool direct = d.tune_us[pi][tb] * float(depth) >= kDirectLaunchUs;
         if (K > 0)
             run_maybe_graph(d, "tb|" + base + "|tb" + std::to_string(tb) + "|" + std::to_string(K), s,
                             [&](hipStream_t cs) {
@@ -1668,7 +1679,8 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                                     left -= kk;
                                 }
                                 if (io_in_graph) unpack(passes % 2 == 1 ? B : A, cs);
-                            });
+                            },
+                            direct);
         iters = K;
         in_b = passes % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;
@@ -1677,6 +1689,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         // multicolour, passes of up to mck sweeps, ping-pong A/B
         const int32_t K = o.max_iters;
         const int32_t passes = (K + mck - 1) / mck;
+        const bool direct = d.mc_us[pi] * float(mck) >= kDirectLaunchUs;
         if (K > 0)
             run_maybe_graph(d, "mcp|" + base + "|" + std::to_string(K), s, [&](hipStream_t cs) {
                 if (io_in_graph) pack(cs);
@@ -1687,19 +1700,22 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                     left -= kk;
                 }
                 if (io_in_graph) unpack(passes % 2 == 1 ? B : A, cs);
-            });
+            }, direct);
         iters = K;
         in_b = passes % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
     } else if (!o.check_quality) {
         const int32_t K = o.max_iters;
+        // one launch per sweep (colour by colour: one per colour, kept in a graph)
+        const bool direct = colour ? mc >= 0 && d.mc_us[pi] >= kDirectLaunchUs
+                                   : cfg >= 0 && d.tune_us[pi][cfg] >= kDirectLaunchUs;
         if (K > 0)
             run_maybe_graph(d, "fixed|" + base + "|" + std::to_string(K), s, [&](hipStream_t cs) {
                 if (io_in_graph) pack(cs);
                 for (int32_t k = 0; k < K; ++k) sweep_once(k % 2 == 0 ? A : B, k % 2 == 0 ? B : A, nullptr, cs);
                 if (io_in_graph) unpack(!in_place && K % 2 == 1 ? B : A, cs);
-            });
+            }, direct);
         iters = K;
         in_b = !in_place && K % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;

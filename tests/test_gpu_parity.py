@@ -578,29 +578,35 @@ def test_calls_on_two_streams_are_ordered_by_the_handle():
         assert torch.equal(x, rx) and torch.equal(y, ry)
 
 
+@pytest.mark.parametrize("graph", ["1", "0"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("scheme", ["jacobi", "multicolor"])
-def test_repeated_fixed_k_calls_on_the_same_arrays(prec, scheme):
-    # a fixed-K call on the arrays of the previous call runs the pack, the
-    # passes and the unpack as one graph: every replay, with eager work and
-    # synchronisation between replays, equals the call on fresh arrays, and K
-    # more sweeps on its result equal 2K sweeps from the start
+def test_repeated_fixed_k_calls_on_the_same_arrays(prec, scheme, graph):
+    # a fixed-K call on the arrays of the previous call issues the pack, the
+    # passes and the unpack together (one graph, or launch by launch): every
+    # replay, with eager work and synchronisation between replays, equals the
+    # call on fresh arrays, and K more sweeps on its result equal 2K sweeps
+    # from the start
     torch = torch_mod()
     from paper_1606_00803_amd import lms
     dt = torch.float64 if prec == "f64" else torch.float32
     m = meshgen.jittered_grid(300, seed=43, land_fraction=0.3)
-    M = lms.Mesh.build_csr(m.n, m.tri)
-    M.reorder("rdr", x0=m.x, y0=m.y)
-    x0 = to_dev(m.x, dt)
-    y0 = to_dev(m.y, dt)
+    os.environ["LMS_GRAPH"] = graph              # read when the handle first touches the device
+    try:
+        M = lms.Mesh.build_csr(m.n, m.tri)
+        M.reorder("rdr", x0=m.x, y0=m.y)
+        x0 = to_dev(m.x, dt)
+        y0 = to_dev(m.y, dt)
 
-    def fresh():
-        x = torch.empty_like(x0)
-        y = torch.empty_like(y0)
-        M.permute(x0, y0, x, y)
-        return x, y
+        def fresh():
+            x = torch.empty_like(x0)
+            y = torch.empty_like(y0)
+            M.permute(x0, y0, x, y)
+            return x, y
 
-    x, y = fresh()
+        x, y = fresh()
+    finally:
+        os.environ.pop("LMS_GRAPH", None)
     for K in (13, 9, 1):                         # odd and even pass counts at depths 1-4
         rx, ry = fresh()
         M.smooth(rx, ry, max_iters=K, check_quality=False, scheme=scheme)
