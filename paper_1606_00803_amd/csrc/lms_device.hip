@@ -701,7 +701,7 @@ void launch_sweep_cfg(int cfg, const DeviceState &d, const Mesh &M, const T *sx,
 // device state (k is ignored) and it writes the tiles' quality sums.
 template <typename T>
 void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T> *src, vec2_t<T> *dst, int32_t k,
-                   hipStream_t s, bool qual = false, int32_t max_iters = 0) {
+                   hipStream_t s, bool qual = false, int32_t max_iters = 0, T *ox = nullptr, T *oy = nullptr) {
     const TBShape t = tb_shape(cfg);
     const DeviceState::TBDev *h = find_tb(d, t);
     if (!h || !h->fits || M.ell_w != t.w) fail(LMS_ERR_STATE, "temporally blocked variant launched without its plan");
@@ -710,6 +710,8 @@ void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T>
         k = t.k;
     }
     if (k < 1 || k > t.k) fail(LMS_ERR_STATE, "temporally blocked pass deeper than its plan");
+    if ((ox == nullptr) != (oy == nullptr) || (qual && ox))
+        fail(LMS_ERR_STATE, "temporally blocked pass: separate outputs need both arrays and no quality");
     if (h->u_max > t.bs * t.r || size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024)
         fail(LMS_ERR_STATE, "temporally blocked plan does not fit the variant");
     if (h->tiles == 0) return;
@@ -719,12 +721,12 @@ void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T>
     case id:                                                                                                   \
         if (qual)                                                                                              \
             k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, true, g != 0><<<h->tiles, bs, lds, s>>>(               \
-                h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, h->qtri_ptr,     \
-                h->qtri, h->qpart, d.st, max_iters);                                                           \
+                h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, nullptr,        \
+                nullptr, h->qtri_ptr, h->qtri, h->qpart, d.st, max_iters);                                     \
         else                                                                                                   \
             k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, false, g != 0><<<h->tiles, bs, lds, s>>>(              \
-                h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, nullptr,        \
-                nullptr, nullptr, nullptr, 0);                                                                 \
+                h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, ox, oy,         \
+                nullptr, nullptr, nullptr, nullptr, 0);                                                        \
         break;
         LMS_TB_CONFIGS(TB)
 #undef TB
@@ -1655,7 +1657,8 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
             launch_sweep2_cfg<T>(cfg, d, M, src, dst, st, cs);
     };
     int32_t iters = 0;
-    bool in_b = false;  // the result sits in B
+    bool in_b = false;        // the result sits in B
+    bool xy_written = false;  // the last pass wrote the result to x, y
     if (small_rows > 0) {
         // every mesh of the batch fits in LDS: all K sweeps in one launch
         const int32_t K = o.max_iters;
@@ -1668,6 +1671,9 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         const int32_t K = o.max_iters, depth = sweep_config_depth(tb);
         const int32_t passes = (K + depth - 1) / depth;
         const bool direct = d.tune_us[pi][tb] * float(depth) >= kDirectLaunchUs;
+        // the last pass writes the result to x, y itself when no graph keeps
+        // x, y beyond this call under a key that does not name them
+        const bool to_xy = io_in_graph || direct || !d.use_graphs;
         if (K > 0)
             run_maybe_graph(d, "tb|" + base + "|tb" + std::to_string(tb) + "|" + std::to_string(K), s,
                             [&](hipStream_t cs) {
@@ -1675,14 +1681,16 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
                                 int32_t left = K;
                                 for (int32_t q = 0; q < passes; ++q) {
                                     const int32_t kk = std::min(left, depth);
-                                    launch_tb_cfg<T>(tb, d, M, q % 2 == 0 ? A : B, q % 2 == 0 ? B : A, kk, cs);
+                                    const bool last = to_xy && q == passes - 1;
+                                    launch_tb_cfg<T>(tb, d, M, q % 2 == 0 ? A : B, q % 2 == 0 ? B : A, kk, cs, false,
+                                                     0, last ? x : nullptr, last ? y : nullptr);
                                     left -= kk;
                                 }
-                                if (io_in_graph) unpack(passes % 2 == 1 ? B : A, cs);
                             },
                             direct);
         iters = K;
         in_b = passes % 2 == 1;
+        xy_written = K > 0 && to_xy;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
     } else if (!o.check_quality && mck > 1) {
@@ -1818,7 +1826,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         r.last_dq = h.last_dq;
         in_b = !in_place && iters % 2 == 1;
     }
-    if (!io_in_graph) {
+    if (!io_in_graph && !xy_written) {
         unpack(in_b ? B : A, s);
         launch_check();
     }

@@ -609,6 +609,10 @@ __device__ __forceinline__ double block_sum(double v, double *s_red);
 // entries of its staged-row list (halo_ptr/halo then cover every staged row),
 // read and written through it.
 //
+// ox, oy (non-null only for the last pass of a fixed-K call without quality):
+// the last sweep writes the own free rows to these separate x and y arrays
+// instead of dst, so no unpack of dst follows.
+//
 // QUAL (the stopping rule, Section 5.1): the pass also evaluates the quality
 // (Section 3.2) of each state it starts a sweep from.  Before sweep j+1 the
 // own rows and ring 1 hold state s+j, and every triangle of the tile (those
@@ -624,6 +628,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
                                                   const int64_t *__restrict__ lidx_ptr,
                                                   const uint16_t *__restrict__ lidx,
                                                   const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst,
+                                                  T *__restrict__ ox, T *__restrict__ oy,
                                                   const int64_t *__restrict__ qtri_ptr,
                                                   const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
                                                   const StopState *__restrict__ st, int32_t max_iters) {
@@ -759,7 +764,15 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
         if (j == k) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (w[r]) dst[G ? halo[hb + tid + BS * r] : b + tid + BS * r] = o[r];
+                if (w[r]) {
+                    const int32_t v = G ? halo[hb + tid + BS * r] : b + tid + BS * r;
+                    if (ox) {
+                        ox[v] = o[r].x;
+                        oy[v] = o[r].y;
+                    } else {
+                        dst[v] = o[r];
+                    }
+                }
         } else {
             __syncthreads();
 #pragma unroll
