@@ -1626,11 +1626,11 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
     const bool in_place = colour && mc < 0;
     const int nb = (M.n + 255) / 256;
     const int small_rows = colour || o.check_quality ? 0 : small;
-    // A fixed-K call on the same x, y as the previous one issues the pack and
-    // the unpack with the passes, in one graph keyed by x and y (or launch by
-    // launch when the launches are long), which removes the gaps around them;
-    // other calls pack and unpack around the passes, so arrays that change
-    // from call to call capture no new graph.
+    // A fixed-K call on the same x, y as the previous one issues the pack (and
+    // the unpack, where one is needed) with the passes, in one graph keyed by
+    // x and y (or launch by launch when the launches are long), which removes
+    // the gaps around them; other calls pack and unpack around the passes, so
+    // arrays that change from call to call capture no new graph.
     const bool fixed_k = !o.check_quality && o.max_iters > 0 && small_rows == 0;
     const bool io_in_graph = fixed_k && d.io_x == x && d.io_y == y;
     if (fixed_k) {
