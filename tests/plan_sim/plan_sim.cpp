@@ -1,0 +1,259 @@
+// CPU simulation of the tile plans that the temporally blocked Jacobi pass
+// and the one-pass multicolour sweep read (host logic, no GPU).
+//
+// A plan lists, per tile, the rows it stages, the rows each sweep of a pass
+// updates and the staging slots of their neighbours.  This program runs the
+// arithmetic of Eq. 1 exactly as those lists direct it (ascending CSR order,
+// one division per row) on one scalar field and compares the result, bit for
+// bit, with plain sweeps over the whole mesh:
+//   - temporally blocked plans: a pass of depth d against d Jacobi sweeps
+//     (Algorithm 1, every free vertex reading the previous sweep);
+//   - multicolour plans: a pass of depth d against d colour-by-colour sweeps
+//     in place (the in-place form of Algorithm 1 under a vertex colouring).
+//
+// Usage: plan_sim <mesh file> <ori|bfs|rdr|random> [plant]
+// Mesh file: int32 n, int64 T, int32 tri[3T], float64 x[n], float64 y[n].
+// Prints one line per plan shape; exits 1 on any mismatch or library error.
+// With "plant", each plan is simulated from a copy in which one own row of
+// the first tile reads its own slot in place of its first neighbour: every
+// fitting shape must then report mismatches (a check of this checker).
+#include <cstdio>
+#include <fstream>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "lms_internal.hpp"
+
+// The plan builders live beside the device runtime; these two hooks belong
+// to it and have nothing to release here.
+namespace lms {
+void destroy_device_state(DeviceState *) {}
+void destroy_reorder_state(ReorderState *) {}
+}  // namespace lms
+
+namespace {
+
+using lms::Mesh;
+
+// One row of Eq. 1 over the values `val` of its neighbours, in CSR order.
+double row_mean(const Mesh &M, int32_t v, const std::vector<double> &val) {
+    double a = 0.0;
+    int c = 0;
+    for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+        a += val[size_t(M.col[size_t(j)])];
+        ++c;
+    }
+    return a / double(c);
+}
+
+std::vector<double> jacobi(const Mesh &M, std::vector<double> p, int sweeps) {
+    for (int s = 0; s < sweeps; ++s) {
+        std::vector<double> q = p;
+        for (int32_t v = 0; v < M.n; ++v)
+            if (!M.fixed[size_t(v)]) q[size_t(v)] = row_mean(M, v, p);
+        p.swap(q);
+    }
+    return p;
+}
+
+std::vector<double> multicolour(const Mesh &M, std::vector<double> p, int sweeps) {
+    for (int s = 0; s < sweeps; ++s)
+        for (int32_t c = 0; c < M.n_colors; ++c)
+            for (int32_t v = 0; v < M.n; ++v)
+                if (!M.fixed[size_t(v)] && M.color[size_t(v)] == c) p[size_t(v)] = row_mean(M, v, p);
+    return p;
+}
+
+// Mean over the padded slots of one plan row (0xFFFF ends the row).
+double slot_mean(const uint16_t *slots, int W, const std::vector<double> &lds, bool &any) {
+    double a = 0.0;
+    int c = 0;
+    for (int q = 0; q < W; ++q)
+        if (slots[q] != 0xFFFFu) {
+            a += lds[slots[q]];
+            ++c;
+        }
+    any = c > 0;
+    return any ? a / double(c) : 0.0;
+}
+
+long count_mismatches(const std::vector<double> &a, const std::vector<double> &b) {
+    long bad = 0;
+    for (size_t i = 0; i < a.size(); ++i) bad += a[i] != b[i];
+    return bad;
+}
+
+// A temporally blocked pass of depth d from p0, as the plan directs it.
+std::vector<double> tb_pass(const Mesh &M, const Mesh::TBPlan &P, const std::vector<double> &p0, int d) {
+    const int W = M.ell_w, k = P.k;
+    std::vector<double> out = p0;
+    for (int32_t t = 0; t < P.tiles; ++t) {
+        const int32_t *rc = &P.ring[size_t(t) * size_t(k + 1)];
+        const int32_t nown = rc[0], nload = rc[d];
+        const int64_t hb = P.halo_ptr[size_t(t)];
+        auto row_of = [&](int32_t sl) {
+            if (P.patches) return P.halo[size_t(hb + sl)];
+            return sl < nown ? P.tile_ptr[size_t(t)] + sl : P.halo[size_t(hb + sl - nown)];
+        };
+        std::vector<double> lds(static_cast<size_t>(nload));
+        for (int32_t sl = 0; sl < nload; ++sl) lds[size_t(sl)] = p0[size_t(row_of(sl))];
+        const uint16_t *lx = P.lidx.data() + size_t(P.lidx_ptr[size_t(t)]) * size_t(W);
+        for (int j = 1; j <= d; ++j) {
+            const int32_t m = rc[d - j];  // rows this sweep updates
+            std::vector<double> next = lds;
+            for (int32_t i = 0; i < m; ++i) {
+                bool any = false;
+                const double v = slot_mean(lx + size_t(i) * size_t(W), W, lds, any);
+                if (any) next[size_t(i)] = v;
+            }
+            lds.swap(next);
+        }
+        for (int32_t sl = 0; sl < nown; ++sl) {
+            const int32_t v = row_of(sl);
+            if (!M.fixed[size_t(v)]) out[size_t(v)] = lds[size_t(sl)];
+        }
+    }
+    return out;
+}
+
+// A one-pass multicolour pass of depth d from p0: sweeps k-d+1..k of the
+// plan, colour by colour in place in the tile's staging area.
+std::vector<double> mc_pass(const Mesh &M, const Mesh::MCPlan &P, const std::vector<double> &p0, int d) {
+    const int W = M.ell_w, C = M.n_colors, k = P.k;
+    std::vector<double> out = p0;
+    for (int32_t t = 0; t < P.tiles; ++t) {
+        const int32_t nown = P.tile_ptr[size_t(t) + 1] - P.tile_ptr[size_t(t)];
+        const int64_t hb = P.halo_ptr[size_t(t)];
+        const int32_t nst = int32_t(P.halo_ptr[size_t(t) + 1] - hb) + (P.patches ? 0 : nown);
+        auto row_of = [&](int32_t sl) {
+            if (P.patches) return P.halo[size_t(hb + sl)];
+            return sl < nown ? P.tile_ptr[size_t(t)] + sl : P.halo[size_t(hb + sl - nown)];
+        };
+        std::vector<double> lds(static_cast<size_t>(nst));
+        for (int32_t sl = 0; sl < nst; ++sl) lds[size_t(sl)] = p0[size_t(row_of(sl))];
+        const int64_t *u = &P.upd_ptr[size_t(t) * size_t(C + 1)];
+        for (int s = k - d + 1; s <= k; ++s)
+            for (int32_t c = 0; c < C; ++c)
+                for (int64_t e = u[c]; e < u[c + 1]; ++e) {
+                    if (k > 1 && !((P.umask[size_t(e)] >> (s - 1)) & 1u)) continue;
+                    bool any = false;
+                    const double v = slot_mean(P.uidx.data() + size_t(e) * size_t(W), W, lds, any);
+                    if (any) lds[P.urow[size_t(e)]] = v;
+                }
+        for (int32_t sl = 0; sl < nown; ++sl) {
+            const int32_t v = row_of(sl);
+            if (!M.fixed[size_t(v)]) out[size_t(v)] = lds[size_t(sl)];
+        }
+    }
+    return out;
+}
+
+// The planted mistakes: the first own row of tile 0 that has neighbours
+// reads its own slot in place of its first neighbour.
+void plant(Mesh::TBPlan &P, int W) {
+    const int32_t nown = P.ring[0];
+    for (int32_t i = 0; i < nown; ++i) {
+        uint16_t *row = P.lidx.data() + size_t(P.lidx_ptr[0] + i) * size_t(W);
+        if (row[0] != 0xFFFFu) {
+            row[0] = uint16_t(i);
+            return;
+        }
+    }
+}
+
+void plant(Mesh::MCPlan &P, int W) {
+    const int32_t nown = P.tile_ptr[1] - P.tile_ptr[0];
+    for (int64_t e = 0; e < P.upd_ptr[size_t(P.colors)]; ++e) {
+        uint16_t *row = P.uidx.data() + size_t(e) * size_t(W);
+        if (P.urow[size_t(e)] < nown && row[0] != 0xFFFFu) {
+            row[0] = P.urow[size_t(e)];
+            return;
+        }
+    }
+}
+
+}  // namespace
+
+int main(int argc, char **argv) {
+    if (argc != 3 && !(argc == 4 && std::string(argv[3]) == "plant")) {
+        std::fprintf(stderr, "usage: plan_sim <mesh file> <ori|bfs|rdr|random> [plant]\n");
+        return 2;
+    }
+    const bool planted = argc == 4;
+    std::ifstream f(argv[1], std::ios::binary);
+    int32_t n = 0;
+    int64_t T = 0;
+    f.read(reinterpret_cast<char *>(&n), sizeof(n));
+    f.read(reinterpret_cast<char *>(&T), sizeof(T));
+    std::vector<int32_t> tri(static_cast<size_t>(3 * T));
+    std::vector<double> x(static_cast<size_t>(n)), y(static_cast<size_t>(n));
+    f.read(reinterpret_cast<char *>(tri.data()), std::streamsize(tri.size() * sizeof(int32_t)));
+    f.read(reinterpret_cast<char *>(x.data()), std::streamsize(x.size() * sizeof(double)));
+    f.read(reinterpret_cast<char *>(y.data()), std::streamsize(y.size() * sizeof(double)));
+    if (!f) {
+        std::fprintf(stderr, "plan_sim: short mesh file\n");
+        return 2;
+    }
+    const std::string ord = argv[2];
+    long total_bad = 0;
+    try {
+        Mesh M;
+        const int64_t v_off[2] = {0, n}, t_off[2] = {0, T};
+        lms::build_mesh(M, n, T, tri.data(), nullptr, 1, v_off, t_off);
+        if (ord == "bfs") {
+            lms::relabel(M, LMS_BFS, lms::order_bfs(M));
+        } else if (ord == "rdr") {
+            std::vector<double> q(static_cast<size_t>(n));
+            lms::vertex_quality_host(M, x.data(), y.data(), q.data());
+            lms::relabel(M, LMS_RDR, lms::order_rdr(M, q.data()));
+        } else if (ord == "random") {
+            lms::relabel(M, LMS_RANDOM, lms::order_random(M, 12345));
+        } else if (ord != "ori") {
+            std::fprintf(stderr, "plan_sim: unknown ordering %s\n", ord.c_str());
+            return 2;
+        }
+        if (M.ell_w <= 0) {
+            std::fprintf(stderr, "plan_sim: mesh has no padded adjacency\n");
+            return 2;
+        }
+        // a field with no structure, so that any wrong neighbour or order shows
+        std::mt19937_64 rng(7);
+        std::uniform_real_distribution<double> U(-1.0, 1.0);
+        std::vector<double> p0(static_cast<size_t>(n));
+        for (auto &v : p0) v = U(rng);
+
+        // temporally blocked plans: {tile size, depth, update cap, staging cap}
+        const int tb_shapes[][4] = {{256, 2, 512, 1024}, {512, 3, 1024, 2048}, {1024, 4, 2048, 2048}};
+        for (int patches = 0; patches < 2; ++patches)
+            for (const auto &c : tb_shapes) {
+                Mesh::TBPlan P = lms::tb_plan(M, c[0], c[1], c[2], c[3], patches != 0);
+                if (planted && P.fits) plant(P, M.ell_w);
+                long bad = 0;
+                if (P.fits)
+                    for (int d = 1; d <= P.k; ++d) bad += count_mismatches(tb_pass(M, P, p0, d), jacobi(M, p0, d));
+                total_bad += bad;
+                std::printf("tb %s ts=%d k=%d fits=%d tiles=%d mismatches=%ld\n", patches ? "patch" : "range", c[0],
+                            c[1], int(P.fits), P.tiles, bad);
+            }
+        // multicolour plans: {tile size, staging cap, update cap, sweeps per pass}
+        const int mc_shapes[][4] = {{128, 1024, 512, 1}, {512, 2048, 1024, 1}, {512, 2048, 1024, 2},
+                                    {256, 2048, 1024, 3}, {1024, 4096, 2048, 2}};
+        for (int patches = 0; patches < 2; ++patches)
+            for (const auto &c : mc_shapes) {
+                Mesh::MCPlan P = lms::mc_plan(M, c[0], c[1], c[2], patches != 0, c[3]);
+                if (planted && P.fits) plant(P, M.ell_w);
+                long bad = 0;
+                if (P.fits)
+                    for (int d = 1; d <= P.k; ++d)
+                        bad += count_mismatches(mc_pass(M, P, p0, d), multicolour(M, p0, d));
+                total_bad += bad;
+                std::printf("mc %s ts=%d k=%d fits=%d tiles=%d mismatches=%ld\n", patches ? "patch" : "range", c[0],
+                            c[3], int(P.fits), P.tiles, bad);
+            }
+    } catch (const lms::Error &e) {
+        std::printf("FAIL %s\n", e.msg.c_str());
+        return 1;
+    }
+    return total_bad == 0 ? 0 : 1;
+}

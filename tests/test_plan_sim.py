@@ -1,0 +1,79 @@
+"""Tile plans of the temporally blocked and one-pass multicolour sweeps,
+simulated on the CPU (host logic, no GPU).
+
+`tests/plan_sim/plan_sim.cpp` links the library's host sources, builds the
+plans the device kernels read, runs Eq. 1 exactly as each plan directs (the
+staged rows, the rows every sweep of a pass updates, their neighbour slots)
+and compares bit for bit with plain sweeps over the whole mesh: Jacobi
+sweeps for the temporally blocked plans, colour-by-colour in-place sweeps
+for the multicolour plans, at every pass depth the plan allows.  A planted
+wrong neighbour slot must make every fitting plan shape fail.
+"""
+from __future__ import annotations
+
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import meshgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LINE = re.compile(r"^(tb|mc) (range|patch) ts=(\d+) k=(\d+) fits=([01]) tiles=(\d+) mismatches=(\d+)$")
+
+
+@pytest.fixture(scope="module")
+def plan_sim(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    out = tmp_path_factory.mktemp("plan_sim") / "plan_sim"
+    csrc = os.path.join(ROOT, "paper_1606_00803_amd", "csrc")
+    subprocess.run([gxx, "-O2", "-std=c++17", "-pthread", f"-I{ROOT}/include", f"-I{csrc}",
+                    os.path.join(ROOT, "tests", "plan_sim", "plan_sim.cpp"), os.path.join(csrc, "lms_host.cpp"),
+                    "-o", str(out)], check=True, timeout=600)
+    return str(out)
+
+
+@pytest.fixture(scope="module")
+def mesh_file(tmp_path_factory):
+    # ocean-like: holes, ragged sizes, ~27k vertices, tiles of 128-1024 rows
+    m = meshgen.jittered_grid(211, 173, seed=17, land_fraction=0.3)
+    path = tmp_path_factory.mktemp("plan_mesh") / "mesh.bin"
+    with open(path, "wb") as fh:
+        np.array([m.n], dtype=np.int32).tofile(fh)
+        np.array([m.T], dtype=np.int64).tofile(fh)
+        np.ascontiguousarray(m.tri, dtype=np.int32).tofile(fh)
+        m.x.astype(np.float64).tofile(fh)
+        m.y.astype(np.float64).tofile(fh)
+    return str(path)
+
+
+def run(plan_sim, mesh_file, *args):
+    r = subprocess.run([plan_sim, mesh_file, *args], capture_output=True, text=True, timeout=300)
+    rows = [LINE.match(line) for line in r.stdout.splitlines()]
+    assert all(rows) and len(rows) == 16, r.stdout + r.stderr
+    return r.returncode, [(g[1], g[2], int(g[3]), int(g[4]), g[5] == "1", int(g[7])) for g in rows]
+
+
+@pytest.mark.parametrize("ordering", ["ori", "bfs", "rdr", "random"])
+def test_plans_reproduce_plain_sweeps_bit_for_bit(plan_sim, mesh_file, ordering):
+    rc, rows = run(plan_sim, mesh_file, ordering)
+    assert rc == 0, rows
+    assert all(bad == 0 for *_, bad in rows), rows
+    fit = [r for r in rows if r[4]]
+    # patch tiles fit under every ordering; row ranges give up on random labels
+    assert sum(1 for r in fit if r[1] == "patch") == 8, rows
+    assert len(fit) >= (8 if ordering == "random" else 12), rows
+    # several sweeps per pass are covered for both plan kinds
+    assert any(r[0] == "tb" and r[3] == 4 for r in fit) and any(r[0] == "mc" and r[3] == 3 for r in fit)
+
+
+def test_a_planted_wrong_slot_is_caught(plan_sim, mesh_file):
+    rc, rows = run(plan_sim, mesh_file, "rdr", "plant")
+    assert rc == 1
+    fit = [r for r in rows if r[4]]
+    assert fit and all(bad > 0 for *_, bad in fit), rows
