@@ -10,13 +10,21 @@
 //     (Algorithm 1, every free vertex reading the previous sweep);
 //   - multicolour plans: a pass of depth d against d colour-by-colour sweeps
 //     in place (the in-place form of Algorithm 1 under a vertex colouring).
+// It also sums the mesh quality (Section 3.2, Algorithm 1) from each plan's
+// triangle records over the staged input coordinates, as the quality-fused
+// passes do, and compares it with the per-vertex definition (relative error
+// q_err; the two sum in different orders).
 //
 // Usage: plan_sim <mesh file> <ori|bfs|rdr|random> [plant]
 // Mesh file: int32 n, int64 T, int32 tri[3T], float64 x[n], float64 y[n].
 // Prints one line per plan shape; exits 1 on any mismatch or library error.
 // With "plant", each plan is simulated from a copy in which one own row of
-// the first tile reads its own slot in place of its first neighbour: every
-// fitting shape must then report mismatches (a check of this checker).
+// the first tile reads its own slot in place of its first neighbour, and the
+// first triangle record counts one triangle too many at its second corner:
+// every fitting shape must then report mismatches and a large q_err (a check
+// of this checker).
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <fstream>
 #include <random>
@@ -149,6 +157,54 @@ std::vector<double> mc_pass(const Mesh &M, const Mesh::MCPlan &P, const std::vec
     return out;
 }
 
+// Edge-length ratio of a triangle: shortest over longest edge (Section 3.2).
+double tri_q(double xa, double ya, double xb, double yb, double xc, double yc) {
+    const double e[3] = {(xb - xa) * (xb - xa) + (yb - ya) * (yb - ya), (xc - xb) * (xc - xb) + (yc - yb) * (yc - yb),
+                         (xa - xc) * (xa - xc) + (ya - yc) * (ya - yc)};
+    const double mn = std::min({e[0], e[1], e[2]}), mx = std::max({e[0], e[1], e[2]});
+    return mx > 0.0 ? std::sqrt(mn) / std::sqrt(mx) : 0.0;
+}
+
+// n times the mesh quality from its definition, in input labels: the sum
+// over vertices of the mean quality of the triangles at each vertex.
+double quality_sum_direct(const Mesh &M, const std::vector<double> &x, const std::vector<double> &y) {
+    std::vector<double> s(size_t(M.n), 0.0);
+    for (int64_t t = 0; t < M.T; ++t) {
+        const int32_t a = M.tri0[size_t(3 * t)], b = M.tri0[size_t(3 * t + 1)], c = M.tri0[size_t(3 * t + 2)];
+        const double q = tri_q(x[size_t(a)], y[size_t(a)], x[size_t(b)], y[size_t(b)], x[size_t(c)], y[size_t(c)]);
+        s[size_t(a)] += q;
+        s[size_t(b)] += q;
+        s[size_t(c)] += q;
+    }
+    double total = 0.0;
+    for (int32_t v = 0; v < M.n; ++v)
+        if (M.tcount0[size_t(v)] > 0) total += s[size_t(v)] / double(M.tcount0[size_t(v)]);
+    return total;
+}
+
+// The same sum from a plan's triangle records: each record names three
+// staging slots of its tile and the triangle counts of the three corners;
+// triangles with only fixed corners are listed apart with their weights.
+template <class Plan, class RowOf>
+double quality_sum_plan(const Plan &P, RowOf row_of, const std::vector<double> &xc, const std::vector<double> &yc) {
+    double total = 0.0;
+    for (int32_t t = 0; t < P.tiles; ++t)
+        for (int64_t i = P.qtri_ptr[size_t(t)]; i < P.qtri_ptr[size_t(t) + 1]; ++i) {
+            const uint32_t w0 = P.qtri[size_t(3 * i)], w1 = P.qtri[size_t(3 * i + 1)], w2 = P.qtri[size_t(3 * i + 2)];
+            const int32_t a = row_of(t, int32_t(w0 & 0xFFFFu)), b = row_of(t, int32_t(w0 >> 16)),
+                          c = row_of(t, int32_t(w1 & 0xFFFFu));
+            const double q = tri_q(xc[size_t(a)], yc[size_t(a)], xc[size_t(b)], yc[size_t(b)], xc[size_t(c)],
+                                   yc[size_t(c)]);
+            total += q * (1.0 / double(w1 >> 16) + 1.0 / double(w2 & 0xFFFFu) + 1.0 / double(w2 >> 16));
+        }
+    for (size_t i = 0; i < P.qc_w.size(); ++i) {
+        const int32_t a = P.qc_ids[3 * i], b = P.qc_ids[3 * i + 1], c = P.qc_ids[3 * i + 2];
+        total += P.qc_w[i] *
+                 tri_q(xc[size_t(a)], yc[size_t(a)], xc[size_t(b)], yc[size_t(b)], xc[size_t(c)], yc[size_t(c)]);
+    }
+    return total;
+}
+
 // The planted mistakes: the first own row of tile 0 that has neighbours
 // reads its own slot in place of its first neighbour.
 void plant(Mesh::TBPlan &P, int W) {
@@ -222,6 +278,14 @@ int main(int argc, char **argv) {
         std::uniform_real_distribution<double> U(-1.0, 1.0);
         std::vector<double> p0(static_cast<size_t>(n));
         for (auto &v : p0) v = U(rng);
+        // the input coordinates in the current labels, and n times their quality
+        std::vector<double> xc(static_cast<size_t>(n)), yc(static_cast<size_t>(n));
+        for (int32_t v = 0; v < n; ++v) {
+            xc[size_t(v)] = x[size_t(M.new2old[size_t(v)])];
+            yc[size_t(v)] = y[size_t(M.new2old[size_t(v)])];
+        }
+        const double q_direct = quality_sum_direct(M, x, y);
+        auto q_err = [&](double q_plan) { return std::fabs(q_plan - q_direct) / q_direct; };
 
         // temporally blocked plans: {tile size, depth, update cap, staging cap}
         const int tb_shapes[][4] = {{256, 2, 512, 1024}, {512, 3, 1024, 2048}, {1024, 4, 2048, 2048}};
@@ -230,11 +294,21 @@ int main(int argc, char **argv) {
                 Mesh::TBPlan P = lms::tb_plan(M, c[0], c[1], c[2], c[3], patches != 0);
                 if (planted && P.fits) plant(P, M.ell_w);
                 long bad = 0;
-                if (P.fits)
+                double qe = -1.0;
+                if (P.fits) {
                     for (int d = 1; d <= P.k; ++d) bad += count_mismatches(tb_pass(M, P, p0, d), jacobi(M, p0, d));
+                    lms::tb_quality_plan(M, P);
+                    if (planted && P.q_fits && !P.qtri.empty()) P.qtri[2] += 1u;
+                    auto row_of = [&](int32_t t, int32_t sl) {
+                        const int32_t nown = P.ring[size_t(t) * size_t(P.k + 1)];
+                        if (P.patches) return P.halo[size_t(P.halo_ptr[size_t(t)] + sl)];
+                        return sl < nown ? P.tile_ptr[size_t(t)] + sl : P.halo[size_t(P.halo_ptr[size_t(t)] + sl - nown)];
+                    };
+                    if (P.q_fits) qe = q_err(quality_sum_plan(P, row_of, xc, yc));
+                }
                 total_bad += bad;
-                std::printf("tb %s ts=%d k=%d fits=%d tiles=%d mismatches=%ld\n", patches ? "patch" : "range", c[0],
-                            c[1], int(P.fits), P.tiles, bad);
+                std::printf("tb %s ts=%d k=%d fits=%d tiles=%d mismatches=%ld q_fits=%d q_err=%.3e\n",
+                            patches ? "patch" : "range", c[0], c[1], int(P.fits), P.tiles, bad, int(P.q_fits), qe);
             }
         // multicolour plans: {tile size, staging cap, update cap, sweeps per pass}
         const int mc_shapes[][4] = {{128, 1024, 512, 1}, {512, 2048, 1024, 1}, {512, 2048, 1024, 2},
@@ -244,12 +318,22 @@ int main(int argc, char **argv) {
                 Mesh::MCPlan P = lms::mc_plan(M, c[0], c[1], c[2], patches != 0, c[3]);
                 if (planted && P.fits) plant(P, M.ell_w);
                 long bad = 0;
-                if (P.fits)
+                double qe = -1.0;
+                if (P.fits) {
                     for (int d = 1; d <= P.k; ++d)
                         bad += count_mismatches(mc_pass(M, P, p0, d), multicolour(M, p0, d));
+                    lms::mc_quality_plan(M, P);
+                    if (planted && P.q_fits && !P.qtri.empty()) P.qtri[2] += 1u;
+                    auto row_of = [&](int32_t t, int32_t sl) {
+                        const int32_t nown = P.tile_ptr[size_t(t) + 1] - P.tile_ptr[size_t(t)];
+                        if (P.patches) return P.halo[size_t(P.halo_ptr[size_t(t)] + sl)];
+                        return sl < nown ? P.tile_ptr[size_t(t)] + sl : P.halo[size_t(P.halo_ptr[size_t(t)] + sl - nown)];
+                    };
+                    if (P.q_fits) qe = q_err(quality_sum_plan(P, row_of, xc, yc));
+                }
                 total_bad += bad;
-                std::printf("mc %s ts=%d k=%d fits=%d tiles=%d mismatches=%ld\n", patches ? "patch" : "range", c[0],
-                            c[3], int(P.fits), P.tiles, bad);
+                std::printf("mc %s ts=%d k=%d fits=%d tiles=%d mismatches=%ld q_fits=%d q_err=%.3e\n",
+                            patches ? "patch" : "range", c[0], c[3], int(P.fits), P.tiles, bad, int(P.q_fits), qe);
             }
     } catch (const lms::Error &e) {
         std::printf("FAIL %s\n", e.msg.c_str());

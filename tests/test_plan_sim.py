@@ -6,8 +6,11 @@ plans the device kernels read, runs Eq. 1 exactly as each plan directs (the
 staged rows, the rows every sweep of a pass updates, their neighbour slots)
 and compares bit for bit with plain sweeps over the whole mesh: Jacobi
 sweeps for the temporally blocked plans, colour-by-colour in-place sweeps
-for the multicolour plans, at every pass depth the plan allows.  A planted
-wrong neighbour slot must make every fitting plan shape fail.
+for the multicolour plans, at every pass depth the plan allows.  It also
+sums the mesh quality from each plan's triangle records, as the
+quality-fused passes do, against the per-vertex definition (Section 3.2).
+A planted wrong neighbour slot and a planted wrong triangle count must make
+every fitting plan shape fail.
 """
 from __future__ import annotations
 
@@ -22,7 +25,8 @@ import pytest
 import meshgen
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LINE = re.compile(r"^(tb|mc) (range|patch) ts=(\d+) k=(\d+) fits=([01]) tiles=(\d+) mismatches=(\d+)$")
+LINE = re.compile(r"^(tb|mc) (range|patch) ts=(\d+) k=(\d+) fits=([01]) tiles=(\d+) mismatches=(\d+) "
+                  r"q_fits=([01]) q_err=(\S+)$")
 
 
 @pytest.fixture(scope="module")
@@ -56,15 +60,18 @@ def run(plan_sim, mesh_file, *args):
     r = subprocess.run([plan_sim, mesh_file, *args], capture_output=True, text=True, timeout=300)
     rows = [LINE.match(line) for line in r.stdout.splitlines()]
     assert all(rows) and len(rows) == 16, r.stdout + r.stderr
-    return r.returncode, [(g[1], g[2], int(g[3]), int(g[4]), g[5] == "1", int(g[7])) for g in rows]
+    return r.returncode, [(g[1], g[2], int(g[3]), int(g[4]), g[5] == "1", int(g[7]), g[8] == "1", float(g[9]))
+                          for g in rows]
 
 
 @pytest.mark.parametrize("ordering", ["ori", "bfs", "rdr", "random"])
 def test_plans_reproduce_plain_sweeps_bit_for_bit(plan_sim, mesh_file, ordering):
     rc, rows = run(plan_sim, mesh_file, ordering)
     assert rc == 0, rows
-    assert all(bad == 0 for *_, bad in rows), rows
+    assert all(r[5] == 0 for r in rows), rows
     fit = [r for r in rows if r[4]]
+    # the fused-quality records sum to the definition's n*Q (another order)
+    assert all(r[6] and 0.0 <= r[7] <= 1e-12 for r in fit), rows
     # patch tiles fit under every ordering; row ranges give up on random labels
     assert sum(1 for r in fit if r[1] == "patch") == 8, rows
     assert len(fit) >= (8 if ordering == "random" else 12), rows
@@ -72,8 +79,8 @@ def test_plans_reproduce_plain_sweeps_bit_for_bit(plan_sim, mesh_file, ordering)
     assert any(r[0] == "tb" and r[3] == 4 for r in fit) and any(r[0] == "mc" and r[3] == 3 for r in fit)
 
 
-def test_a_planted_wrong_slot_is_caught(plan_sim, mesh_file):
+def test_planted_mistakes_are_caught(plan_sim, mesh_file):
     rc, rows = run(plan_sim, mesh_file, "rdr", "plant")
     assert rc == 1
     fit = [r for r in rows if r[4]]
-    assert fit and all(bad > 0 for *_, bad in fit), rows
+    assert fit and all(r[5] > 0 and r[6] and r[7] > 1e-9 for r in fit), rows
