@@ -6,6 +6,7 @@
 // arithmetic of Eq. 1 exactly as those lists direct it (ascending CSR order,
 // one division per row) on one scalar field and compares the result, bit for
 // bit, with plain sweeps over the whole mesh:
+//   - halo plans (one sweep per launch): one Jacobi sweep;
 //   - temporally blocked plans: a pass of depth d against d Jacobi sweeps
 //     (Algorithm 1, every free vertex reading the previous sweep);
 //   - multicolour plans: a pass of depth d against d colour-by-colour sweeps
@@ -120,6 +121,27 @@ std::vector<double> tb_pass(const Mesh &M, const Mesh::TBPlan &P, const std::vec
         for (int32_t sl = 0; sl < nown; ++sl) {
             const int32_t v = row_of(sl);
             if (!M.fixed[size_t(v)]) out[size_t(v)] = lds[size_t(sl)];
+        }
+    }
+    return out;
+}
+
+// One Jacobi sweep from p0 through a halo plan: tile t owns rows
+// [t*ts, (t+1)*ts) at slots 0..ts-1 and stages its halo list after them.
+std::vector<double> halo_sweep(const Mesh &M, const Mesh::HaloPlan &H, const std::vector<double> &p0) {
+    const int W = M.ell_w, ts = H.ts;
+    std::vector<double> out = p0;
+    const int32_t tiles = int32_t(H.halo_ptr.size()) - 1;
+    for (int32_t t = 0; t < tiles; ++t) {
+        const int32_t b = t * ts, e = std::min(M.n, b + ts);
+        const int32_t hb = H.halo_ptr[size_t(t)], nh = H.halo_ptr[size_t(t) + 1] - hb;
+        std::vector<double> lds(static_cast<size_t>(ts + nh), 0.0);
+        for (int32_t v = b; v < e; ++v) lds[size_t(v - b)] = p0[size_t(v)];
+        for (int32_t i = 0; i < nh; ++i) lds[size_t(ts + i)] = p0[size_t(H.halo[size_t(hb + i)])];
+        for (int32_t v = b; v < e; ++v) {
+            bool any = false;
+            const double m = slot_mean(H.lidx.data() + size_t(v) * size_t(W), W, lds, any);
+            if (any) out[size_t(v)] = m;
         }
     }
     return out;
@@ -287,6 +309,21 @@ int main(int argc, char **argv) {
         const double q_direct = quality_sum_direct(M, x, y);
         auto q_err = [&](double q_plan) { return std::fabs(q_plan - q_direct) / q_direct; };
 
+        // single-sweep halo plans: {tile size}
+        for (int ts : {128, 256}) {
+            Mesh::HaloPlan H = lms::halo_plan(M, ts);
+            if (planted) {  // the first row with neighbours reads its own slot
+                for (size_t r = 0; r < H.lidx.size(); r += size_t(M.ell_w))
+                    if (H.lidx[r] != 0xFFFFu) {
+                        H.lidx[r] = uint16_t((r / size_t(M.ell_w)) % size_t(ts));
+                        break;
+                    }
+            }
+            const long bad = count_mismatches(halo_sweep(M, H, p0), jacobi(M, p0, 1));
+            total_bad += bad;
+            std::printf("halo range ts=%d k=1 fits=1 tiles=%d mismatches=%ld q_fits=0 q_err=-1\n", ts,
+                        int(H.halo_ptr.size()) - 1, bad);
+        }
         // temporally blocked plans: {tile size, depth, update cap, staging cap}
         const int tb_shapes[][4] = {{256, 2, 512, 1024}, {512, 3, 1024, 2048}, {1024, 4, 2048, 2048}};
         for (int patches = 0; patches < 2; ++patches)

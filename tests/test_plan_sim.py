@@ -5,7 +5,7 @@ simulated on the CPU (host logic, no GPU).
 plans the device kernels read, runs Eq. 1 exactly as each plan directs (the
 staged rows, the rows every sweep of a pass updates, their neighbour slots)
 and compares bit for bit with plain sweeps over the whole mesh: Jacobi
-sweeps for the temporally blocked plans, colour-by-colour in-place sweeps
+sweeps for the halo and temporally blocked plans, colour-by-colour in-place sweeps
 for the multicolour plans, at every pass depth the plan allows.  It also
 sums the mesh quality from each plan's triangle records, as the
 quality-fused passes do, against the per-vertex definition (Section 3.2).
@@ -25,7 +25,7 @@ import pytest
 import meshgen
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LINE = re.compile(r"^(tb|mc) (range|patch) ts=(\d+) k=(\d+) fits=([01]) tiles=(\d+) mismatches=(\d+) "
+LINE = re.compile(r"^(halo|tb|mc) (range|patch) ts=(\d+) k=(\d+) fits=([01]) tiles=(\d+) mismatches=(\d+) "
                   r"q_fits=([01]) q_err=(\S+)$")
 
 
@@ -59,7 +59,7 @@ def mesh_file(tmp_path_factory):
 def run(plan_sim, mesh_file, *args):
     r = subprocess.run([plan_sim, mesh_file, *args], capture_output=True, text=True, timeout=300)
     rows = [LINE.match(line) for line in r.stdout.splitlines()]
-    assert all(rows) and len(rows) == 16, r.stdout + r.stderr
+    assert all(rows) and len(rows) == 18, r.stdout + r.stderr
     return r.returncode, [(g[1], g[2], int(g[3]), int(g[4]), g[5] == "1", int(g[7]), g[8] == "1", float(g[9]))
                           for g in rows]
 
@@ -71,10 +71,10 @@ def test_plans_reproduce_plain_sweeps_bit_for_bit(plan_sim, mesh_file, ordering)
     assert all(r[5] == 0 for r in rows), rows
     fit = [r for r in rows if r[4]]
     # the fused-quality records sum to the definition's n*Q (another order)
-    assert all(r[6] and 0.0 <= r[7] <= 1e-12 for r in fit), rows
+    assert all(r[6] and 0.0 <= r[7] <= 1e-12 for r in fit if r[0] != "halo"), rows
     # patch tiles fit under every ordering; row ranges give up on random labels
     assert sum(1 for r in fit if r[1] == "patch") == 8, rows
-    assert len(fit) >= (8 if ordering == "random" else 12), rows
+    assert len(fit) >= (10 if ordering == "random" else 14), rows
     # several sweeps per pass are covered for both plan kinds
     assert any(r[0] == "tb" and r[3] == 4 for r in fit) and any(r[0] == "mc" and r[3] == 3 for r in fit)
 
@@ -83,4 +83,5 @@ def test_planted_mistakes_are_caught(plan_sim, mesh_file):
     rc, rows = run(plan_sim, mesh_file, "rdr", "plant")
     assert rc == 1
     fit = [r for r in rows if r[4]]
-    assert fit and all(r[5] > 0 and r[6] and r[7] > 1e-9 for r in fit), rows
+    assert fit and all(r[5] > 0 for r in fit), rows
+    assert all(r[6] and r[7] > 1e-9 for r in fit if r[0] != "halo"), rows
