@@ -85,3 +85,21 @@ def test_planted_mistakes_are_caught(plan_sim, mesh_file):
     fit = [r for r in rows if r[4]]
     assert fit and all(r[5] > 0 for r in fit), rows
     assert all(r[6] and r[7] > 1e-9 for r in fit if r[0] != "halo"), rows
+
+
+def test_plan_builders_under_address_and_undefined_behaviour_sanitizers(tmp_path, mesh_file):
+    # the host plan builders and the simulation, built with the sanitizers
+    # (host code only), on the orderings whose plans scatter the most
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    exe = tmp_path / "plan_sim_san"
+    csrc = os.path.join(ROOT, "paper_1606_00803_amd", "csrc")
+    subprocess.run([gxx, "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                    "-std=c++17", "-pthread", f"-I{ROOT}/include", f"-I{csrc}",
+                    os.path.join(ROOT, "tests", "plan_sim", "plan_sim.cpp"), os.path.join(csrc, "lms_host.cpp"),
+                    "-o", str(exe)], check=True, timeout=900)
+    for ordering in ("rdr", "random"):
+        r = subprocess.run([str(exe), mesh_file, ordering], capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+        assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
