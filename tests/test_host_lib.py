@@ -309,3 +309,9 @@ def test_reuse_profile_ranks_the_bulk_of_accesses_as_the_paper_does():
         q75[kind], lines[kind] = p["quantiles"][0], p["lines_per_wave"]
     assert q75["rdr"] < min(q75["ori"], q75["bfs"]) and max(q75["ori"], q75["bfs"]) < q75["random"], q75
     assert lines["random"] > 4 * max(lines["ori"], lines["bfs"], lines["rdr"]), lines
+
+
+def test_a_missing_library_fails_loudly(tmp_path):
+    # no fallback: without the built library every entry point is unavailable
+    with pytest.raises(OSError, match="not found"):
+        lms.load(str(tmp_path / "liblms.so"))
