@@ -396,14 +396,19 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
         row_ptr[k + 1] = int32_t(nnz);
     }
     resize_or_fail(col, size_t(nnz));
-    for (int32_t k = 0; k < n; ++k) {
-        if (fx[k]) continue;
-        const int32_t v = new2old[k];
-        int32_t *dst = col.data() + row_ptr[k];
-        int64_t d = 0;
-        for (int64_t j = M.adj_ptr0[v]; j < M.adj_ptr0[v + 1]; ++j) dst[d++] = old2new[M.adj0[j]];
-        std::sort(dst, dst + d);
-    }
+    // every row below is filled from the input arrays alone: rows, entries
+    // and triangles split over threads give the same arrays
+    const int row_workers = host_threads(n / 256);
+    parallel_runs(n, row_workers, [&](int, int64_t first, int64_t last) {
+        for (int64_t k = first; k < last; ++k) {
+            if (fx[size_t(k)]) continue;
+            const int32_t v = new2old[size_t(k)];
+            int32_t *dst = col.data() + row_ptr[size_t(k)];
+            int64_t d = 0;
+            for (int64_t j = M.adj_ptr0[v]; j < M.adj_ptr0[v + 1]; ++j) dst[d++] = old2new[M.adj0[j]];
+            std::sort(dst, dst + d);
+        }
+    });
 
     // padded copy of the smoothing adjacency for the offset-free sweep
     // variants, row-major (entry k of row v at ell[v*W + k], -1 past the
@@ -413,38 +418,46 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
     if (M.max_degree <= 16) {
         ell_w = M.max_degree <= 8 ? 8 : (M.max_degree <= 12 ? 12 : 16);
         resize_or_fail(ell, size_t(ell_w) * size_t(n));
-        std::fill(ell.begin(), ell.end(), -1);
-        for (int32_t k = 0; k < n; ++k)
-            for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j) ell[size_t(k) * size_t(ell_w) + size_t(j - row_ptr[k])] = col[j];
+        parallel_runs(n, row_workers, [&](int, int64_t first, int64_t last) {
+            std::fill(ell.begin() + first * ell_w, ell.begin() + last * ell_w, -1);
+            for (int64_t k = first; k < last; ++k)
+                for (int32_t j = row_ptr[size_t(k)]; j < row_ptr[size_t(k) + 1]; ++j)
+                    ell[size_t(k) * size_t(ell_w) + size_t(j - row_ptr[size_t(k)])] = col[size_t(j)];
+        });
     }
 
     // triangles: counting sort by smallest new id, stable in input index
     const int64_t T = M.T;
     std::vector<int64_t> bucket(size_t(n) + 1, 0);
     std::vector<int32_t> key(static_cast<size_t>(T));
-    for (int64_t t = 0; t < T; ++t) {
-        const int32_t a = old2new[M.tri0[3 * t]], b = old2new[M.tri0[3 * t + 1]], c = old2new[M.tri0[3 * t + 2]];
-        key[t] = std::min(a, std::min(b, c));
-        bucket[key[t] + 1]++;
-    }
+    const int tri_workers = host_threads(T / 256);
+    parallel_runs(T, tri_workers, [&](int, int64_t first, int64_t last) {
+        for (int64_t t = first; t < last; ++t) {
+            const int32_t a = old2new[M.tri0[3 * t]], b = old2new[M.tri0[3 * t + 1]], c = old2new[M.tri0[3 * t + 2]];
+            key[size_t(t)] = std::min(a, std::min(b, c));
+        }
+    });
+    for (int64_t t = 0; t < T; ++t) bucket[key[size_t(t)] + 1]++;
     for (int32_t k = 0; k < n; ++k) bucket[k + 1] += bucket[k];
     std::vector<int64_t> torder(static_cast<size_t>(T));
     for (int64_t t = 0; t < T; ++t) torder[bucket[key[t]]++] = t;
     std::vector<int32_t> ta(static_cast<size_t>(T)), tb(static_cast<size_t>(T)), tc(static_cast<size_t>(T)),
         tmesh(static_cast<size_t>(T));
     std::vector<double> tw(static_cast<size_t>(T));
-    for (int64_t i = 0; i < T; ++i) {
-        const int64_t t = torder[i];
-        const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
-        ta[i] = old2new[a];
-        tb[i] = old2new[b];
-        tc[i] = old2new[c];
-        // weight of q_t in the global mean: (1/|V|) sum over its corners of
-        // 1/|T(v)| (the 1/|V| is applied after the sum)
-        tw[i] = 1.0 / double(M.tcount0[a]) + 1.0 / double(M.tcount0[b]) + 1.0 / double(M.tcount0[c]);
-        // mesh index: meshes own contiguous triangle ranges in input order
-        tmesh[i] = int32_t(std::upper_bound(M.t_off.begin(), M.t_off.end(), t) - M.t_off.begin() - 1);
-    }
+    parallel_runs(T, tri_workers, [&](int, int64_t first, int64_t last) {
+        for (int64_t i = first; i < last; ++i) {
+            const int64_t t = torder[size_t(i)];
+            const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
+            ta[size_t(i)] = old2new[a];
+            tb[size_t(i)] = old2new[b];
+            tc[size_t(i)] = old2new[c];
+            // weight of q_t in the global mean: (1/|V|) sum over its corners
+            // of 1/|T(v)| (the 1/|V| is applied after the sum)
+            tw[size_t(i)] = 1.0 / double(M.tcount0[a]) + 1.0 / double(M.tcount0[b]) + 1.0 / double(M.tcount0[c]);
+            // mesh index: meshes own contiguous triangle ranges in input order
+            tmesh[size_t(i)] = int32_t(std::upper_bound(M.t_off.begin(), M.t_off.end(), t) - M.t_off.begin() - 1);
+        }
+    });
     // packed 16-byte triangle record for the quality pass: the corners and the
     // three triangle counts, from which the pass recomputes w_t exactly as above
     std::vector<int32_t> trec;
@@ -453,14 +466,16 @@ void relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old) {
         for (int32_t v = 0; v < n && small; ++v) small = M.tcount0[v] <= 1023;
         if (small) {
             resize_or_fail(trec, size_t(4) * size_t(T));
-            for (int64_t i = 0; i < T; ++i) {
-                const int64_t t = torder[i];
-                const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
-                trec[4 * i] = ta[i];
-                trec[4 * i + 1] = tb[i];
-                trec[4 * i + 2] = tc[i];
-                trec[4 * i + 3] = M.tcount0[a] | (M.tcount0[b] << 10) | (M.tcount0[c] << 20);
-            }
+            parallel_runs(T, tri_workers, [&](int, int64_t first, int64_t last) {
+                for (int64_t i = first; i < last; ++i) {
+                    const int64_t t = torder[size_t(i)];
+                    const int32_t a = M.tri0[3 * t], b = M.tri0[3 * t + 1], c = M.tri0[3 * t + 2];
+                    trec[size_t(4 * i)] = ta[size_t(i)];
+                    trec[size_t(4 * i + 1)] = tb[size_t(i)];
+                    trec[size_t(4 * i + 2)] = tc[size_t(i)];
+                    trec[size_t(4 * i + 3)] = M.tcount0[a] | (M.tcount0[b] << 10) | (M.tcount0[c] << 20);
+                }
+            });
         }
     }
     std::vector<int32_t> vt_ptr(size_t(n) + 1, 0), vt(static_cast<size_t>(3 * T));
@@ -510,11 +525,13 @@ void adopt_relabel(Mesh &M, lms_ordering kind, std::vector<int32_t> new2old, std
         std::fill(color_ell.begin(), color_ell.end(), -1);
         for (int32_t c = 0; c < M.n_colors; ++c) {
             const int64_t base = int64_t(ell_w) * color_ptr[c], cnt = color_ptr[c + 1] - color_ptr[c];
-            for (int64_t i = 0; i < cnt; ++i) {
-                const int32_t k = color_list[size_t(color_ptr[c] + i)];
-                for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j)
-                    color_ell[size_t(base + int64_t(j - row_ptr[k]) * cnt + i)] = col[j];
-            }
+            parallel_runs(cnt, host_threads(cnt / 256), [&](int, int64_t first, int64_t last) {
+                for (int64_t i = first; i < last; ++i) {
+                    const int32_t k = color_list[size_t(color_ptr[c] + i)];
+                    for (int32_t j = row_ptr[k]; j < row_ptr[k + 1]; ++j)
+                        color_ell[size_t(base + int64_t(j - row_ptr[k]) * cnt + i)] = col[size_t(j)];
+                }
+            });
         }
     }
 

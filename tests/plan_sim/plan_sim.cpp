@@ -25,6 +25,7 @@
 // every fitting shape must then report mismatches and a large q_err (a check
 // of this checker).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <fstream>
@@ -227,6 +228,59 @@ double quality_sum_plan(const Plan &P, RowOf row_of, const std::vector<double> &
     return total;
 }
 
+// The current-label arrays a relabelling installs, checked against the CSR
+// and the input triangles: the padded and colour-major copies, the sorted
+// triangle list with its weights and packed records, and the vertex ->
+// triangle lists.  Returns the number of wrong entries.
+long check_relabel(const Mesh &M) {
+    const int32_t n = M.n, W = M.ell_w;
+    long bad = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t deg = M.row_ptr[k + 1] - M.row_ptr[k];
+        for (int32_t j = 0; j < W; ++j)
+            bad += M.ell[size_t(k) * size_t(W) + size_t(j)] != (j < deg ? M.col[size_t(M.row_ptr[k] + j)] : -1);
+    }
+    for (int32_t c = 0; c < M.n_colors; ++c) {
+        const int64_t cnt = M.color_ptr[c + 1] - M.color_ptr[c];
+        for (int64_t i = 0; i < cnt; ++i) {
+            const int32_t k = M.color_list[size_t(M.color_ptr[c] + i)];
+            const int32_t deg = M.row_ptr[k + 1] - M.row_ptr[k];
+            bad += M.color[size_t(k)] != c;
+            for (int32_t j = 0; j < W; ++j)
+                bad += M.color_ell[size_t(int64_t(W) * M.color_ptr[c] + j * cnt + i)] !=
+                       (j < deg ? M.col[size_t(M.row_ptr[k] + j)] : -1);
+        }
+    }
+    // triangles: ascending smallest corner, and back in input labels a
+    // permutation of the input triangles
+    std::vector<std::array<int32_t, 3>> back(size_t(M.T)), in(size_t(M.T));
+    for (int64_t i = 0; i < M.T; ++i) {
+        const int32_t a = M.ta[size_t(i)], b = M.tb[size_t(i)], c = M.tc[size_t(i)];
+        if (i > 0) bad += std::min({a, b, c}) < std::min({M.ta[size_t(i - 1)], M.tb[size_t(i - 1)], M.tc[size_t(i - 1)]});
+        const int32_t oa = M.new2old[size_t(a)], ob = M.new2old[size_t(b)], oc = M.new2old[size_t(c)];
+        back[size_t(i)] = {oa, ob, oc};
+        in[size_t(i)] = {M.tri0[size_t(3 * i)], M.tri0[size_t(3 * i + 1)], M.tri0[size_t(3 * i + 2)]};
+        bad += M.tw[size_t(i)] != 1.0 / double(M.tcount0[size_t(oa)]) + 1.0 / double(M.tcount0[size_t(ob)]) +
+                                      1.0 / double(M.tcount0[size_t(oc)]);
+        if (!M.trec.empty())
+            bad += M.trec[size_t(4 * i)] != a || M.trec[size_t(4 * i + 1)] != b || M.trec[size_t(4 * i + 2)] != c ||
+                   M.trec[size_t(4 * i + 3)] !=
+                       (M.tcount0[size_t(oa)] | (M.tcount0[size_t(ob)] << 10) | (M.tcount0[size_t(oc)] << 20));
+    }
+    std::sort(back.begin(), back.end());
+    std::sort(in.begin(), in.end());
+    bad += back != in;
+    // vertex -> triangles: every triangle at its three corners, ascending
+    for (int32_t v = 0; v < n; ++v)
+        for (int32_t e = M.vt_ptr[v]; e < M.vt_ptr[v + 1]; ++e) {
+            const int32_t t = M.vt[size_t(e)];
+            bad += M.ta[size_t(t)] != v && M.tb[size_t(t)] != v && M.tc[size_t(t)] != v;
+            if (e > M.vt_ptr[v]) bad += t <= M.vt[size_t(e - 1)];
+        }
+    bad += M.vt_ptr[n] != 3 * M.T;
+    return bad;
+}
+
 // The planted mistakes: the first own row of tile 0 that has neighbours
 // reads its own slot in place of its first neighbour.
 void plant(Mesh::TBPlan &P, int W) {
@@ -295,6 +349,9 @@ int main(int argc, char **argv) {
             std::fprintf(stderr, "plan_sim: mesh has no padded adjacency\n");
             return 2;
         }
+        const long relabel_bad = check_relabel(M);
+        total_bad += relabel_bad;
+        std::printf("relabel wrong=%ld\n", relabel_bad);
         // a field with no structure, so that any wrong neighbour or order shows
         std::mt19937_64 rng(7);
         std::uniform_real_distribution<double> U(-1.0, 1.0);

@@ -10,7 +10,10 @@ for the multicolour plans, at every pass depth the plan allows.  It also
 sums the mesh quality from each plan's triangle records, as the
 quality-fused passes do, against the per-vertex definition (Section 3.2).
 A planted wrong neighbour slot and a planted wrong triangle count must make
-every fitting plan shape fail.
+every fitting plan shape fail.  Before the plans, the arrays the relabelling
+installs (padded and colour-major adjacency, the sorted triangle list with
+its weights and records, the vertex -> triangle lists) are checked against
+the CSR and the input triangles.
 """
 from __future__ import annotations
 
@@ -58,7 +61,10 @@ def mesh_file(tmp_path_factory):
 
 def run(plan_sim, mesh_file, *args):
     r = subprocess.run([plan_sim, mesh_file, *args], capture_output=True, text=True, timeout=300)
-    rows = [LINE.match(line) for line in r.stdout.splitlines()]
+    lines = r.stdout.splitlines()
+    # the arrays the relabelling installed (padded copies, triangles, lists)
+    assert lines and lines[0] == "relabel wrong=0", r.stdout + r.stderr
+    rows = [LINE.match(line) for line in lines[1:]]
     assert all(rows) and len(rows) == 18, r.stdout + r.stderr
     return r.returncode, [(g[1], g[2], int(g[3]), int(g[4]), g[5] == "1", int(g[7]), g[8] == "1", float(g[9]))
                           for g in rows]
