@@ -116,7 +116,8 @@ void lms_smooth_opts_default(lms_smooth_opts *o);
 lms_status lms_build_csr(int32_t n, int64_t n_tri, const int32_t *tri,
                          const uint8_t *fixed, lms_mesh_t *out);
 
-/* Build one handle holding n_mesh independent meshes back to back.
+/* Build one handle holding n_mesh independent meshes back to back (Algorithm
+ * 1's inputs V and T for each mesh; neighbours of Eq. 1 within each mesh).
  *   v_off  host int64[n_mesh+1], v_off[0] = 0, mesh i owns vertices
  *          v_off[i] .. v_off[i+1]-1 (total < 2^31)
  *   t_off  host int64[n_mesh+1], mesh i owns triangles t_off[i] .. t_off[i+1]-1
@@ -162,7 +163,11 @@ lms_status lms_reorder_device(lms_mesh_t m, lms_ordering kind, uint64_t seed,
  * Same as lms_reorder(LMS_RDR) with q in place of the computed qualities. */
 lms_status lms_reorder_with_quality(lms_mesh_t m, const double *q, int32_t *new2old);
 
-/* Gather coordinates between input labels and the handle's current labels.
+/* Gather coordinates between input labels and the handle's current labels:
+ * the permutation apply of Algorithm 2 (its V_new[next_num] <- V[i]) for
+ * vertex data, so that the sweep of Eq. 1 runs on the reordered mesh, and its
+ * inverse to bring results back (the Figure 4 caption: the smoothing itself
+ * does not depend on the ordering).
  *   sx, sy  device source arrays [n];  dx, dy  device destinations [n]
  *   inverse 0: dx[k] = sx[new2old[k]] (input -> current labels)
  *           1: dx[new2old[k]] = sx[k] (current -> input labels)
@@ -213,7 +218,10 @@ lms_status lms_sweep(lms_mesh_t m, const void *sx, const void *sy, void *dx, voi
 lms_status lms_quality(lms_mesh_t m, const void *x, const void *y, lms_precision p,
                        double *q_global, double *q_vertex, void *stream);
 
-/* Per-mesh quality of a batched handle: q_mesh host float64[n_mesh] out. */
+/* Per-mesh quality of a batched handle (Section 3.2's mesh quality, Algorithm
+ * 1's global mean, taken over each mesh's own vertices and triangles):
+ * q_mesh host float64[n_mesh] out.  Same arguments and errors as lms_quality;
+ * synchronises the stream. */
 lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_precision p,
                                double *q_mesh, void *stream);
 
@@ -261,9 +269,21 @@ lms_status lms_get_vertex_data(lms_mesh_t m, uint8_t *fixed, int32_t *color);
 /* Current ordering as new2old (host int32[n]). */
 lms_status lms_get_order(lms_mesh_t m, int32_t *new2old);
 
-/* Vertex qualities computed on the host in float64 from INPUT-label
- * coordinates (the qualities RDR sorts by): q host float64[n] out. */
+/* Vertex qualities (Section 3.2: mean over a vertex's triangles of the
+ * shortest / longest edge ratio) computed on the host in float64 from
+ * INPUT-label coordinates, the qualities RDR sorts by (Algorithm 2):
+ * q host float64[n] out. */
 lms_status lms_host_vertex_quality(lms_mesh_t m, const double *x, const double *y, double *q);
+
+/* Statistics of lms_reuse_profile. */
+typedef struct lms_reuse_stats {
+    int64_t accesses;           /* trace length */
+    int64_t cold;               /* first accesses */
+    int64_t max;                /* largest reuse distance */
+    double mean;                /* mean reuse distance of the other accesses */
+    double lines_per_wave;
+    int64_t max_lines_per_wave;
+} lms_reuse_stats;
 
 /* Locality of the current ordering (Section 2, reuse distance and cache
  * misses; the quantiles of Table 2), computed on the host.  The trace is one
@@ -281,15 +301,6 @@ lms_status lms_host_vertex_quality(lms_mesh_t m, const double *x, const double *
  *   stats      host out
  * Fails with LMS_ERR_ARG for a fraction outside [0, 1] or non-positive sizes,
  * and LMS_ERR_STATE when the trace exceeds 2^31 accesses. */
-typedef struct lms_reuse_stats {
-    int64_t accesses;           /* trace length */
-    int64_t cold;               /* first accesses */
-    int64_t max;                /* largest reuse distance */
-    double mean;                /* mean reuse distance of the other accesses */
-    double lines_per_wave;
-    int64_t max_lines_per_wave;
-} lms_reuse_stats;
-
 lms_status lms_reuse_profile(lms_mesh_t m, const double *fractions, int32_t nfrac, int64_t *quantiles,
                              int32_t line_bytes, int32_t record_bytes, lms_reuse_stats *stats);
 

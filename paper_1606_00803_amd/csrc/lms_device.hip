@@ -38,6 +38,7 @@ namespace {
 constexpr int kQualBS = 256;
 constexpr int kQualMaxBlocks = 8192;
 constexpr int kChunk = 16;  // sweeps per captured chunk under the stopping rule (even)
+constexpr size_t kMaxGraphs = 16;  // captured graphs cached per handle
 
 struct GraphEntry {
     std::string key;
@@ -1130,30 +1131,58 @@ void run_maybe_graph(DeviceState &d, const std::string &key, hipStream_t s, F bo
         launch_check();
         return;
     }
-    for (auto &g : d.graphs)
-        if (g.key == key) {
-            HIP_CHECK(hipGraphLaunch(g.exec, s));
+    for (size_t i = 0; i < d.graphs.size(); ++i)
+        if (d.graphs[i].key == key) {
+            // least recently used last out: a hit moves to the back
+            if (i + 1 != d.graphs.size()) {
+                GraphEntry g = d.graphs[i];
+                d.graphs.erase(d.graphs.begin() + std::ptrdiff_t(i));
+                d.graphs.push_back(g);
+            }
+            HIP_CHECK(hipGraphLaunch(d.graphs.back().exec, s));
             return;
         }
     GraphEntry g;
     g.key = key;
     HIP_CHECK(hipStreamBeginCapture(d.cap, hipStreamCaptureModeRelaxed));
-    body(d.cap);
+    try {
+        body(d.cap);
+    } catch (...) {
+        // end the capture whatever body threw, so the capture stream stays usable
+        hipGraph_t partial = nullptr;
+        (void)hipStreamEndCapture(d.cap, &partial);
+        if (partial) (void)hipGraphDestroy(partial);
+        (void)hipGetLastError();
+        throw;
+    }
     hipError_t le = hipGetLastError();
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(d.cap, &graph);
-    if (le != hipSuccess) {
+    if (le != hipSuccess || ce != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
-        fail(LMS_ERR_HIP, std::string("kernel launch failed during capture: ") + hipGetErrorString(le));
+        if (le != hipSuccess)
+            fail(LMS_ERR_HIP, std::string("kernel launch failed during capture: ") + hipGetErrorString(le));
+        fail(LMS_ERR_HIP, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(ce));
     }
-    if (ce != hipSuccess) fail(LMS_ERR_HIP, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(ce));
     g.graph = graph;
     hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
         (void)hipGraphDestroy(graph);
         fail(LMS_ERR_HIP, std::string("hipGraphInstantiate failed: ") + hipGetErrorString(ie));
     }
-    if (d.graphs.size() >= 16) {
+    if (d.graphs.size() >= kMaxGraphs) {
+        // the evicted graph may still run: from an earlier call (last_done)
+        // or from this call on s.  Wait for both before destroying it.
+        hipError_t we = hipSuccess;
+        if (d.last_valid) we = hipEventSynchronize(d.last_done);
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (we == hipSuccess) we = hipStreamIsCapturing(s, &cs);
+        if (we == hipSuccess && cs == hipStreamCaptureStatusNone) we = hipStreamSynchronize(s);
+        if (we != hipSuccess) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+            HIP_CHECK(we);
+        }
         (void)hipGraphExecDestroy(d.graphs.front().exec);
         (void)hipGraphDestroy(d.graphs.front().graph);
         d.graphs.erase(d.graphs.begin());

@@ -15,6 +15,8 @@
 #include <numeric>
 #include <thread>
 
+#include <sched.h>
+
 #include "lms_internal.hpp"
 
 namespace lms {
@@ -33,28 +35,47 @@ void resize_or_fail(std::vector<T> &v, size_t n) {
 }
 
 
-int host_threads(int64_t work_items) {
+// CPUs this process may run on (its affinity mask), at least 1.
+int host_cpus() {
+    cpu_set_t set;
+    CPU_ZERO(&set);
+    if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+        const int c = CPU_COUNT(&set);
+        if (c > 0) return c;
+    }
     const unsigned hw = std::thread::hardware_concurrency();
-    const int64_t t = std::min<int64_t>(std::min<int64_t>(hw == 0 ? 1 : hw, 16), std::max<int64_t>(1, work_items / 64));
+    return hw == 0 ? 1 : int(hw);
+}
+
+int host_threads(int64_t work_items) {
+    const int64_t t = std::min<int64_t>(std::min<int64_t>(host_cpus(), 16), std::max<int64_t>(1, work_items / 64));
     return int(std::max<int64_t>(1, t));
 }
 
 // Runs f(worker, first, last) over [0, items) split into contiguous runs,
-// one thread each; rethrows the first exception.
+// one thread each; rethrows the first exception.  When a thread cannot be
+// started (a process or thread limit), the runs left over execute on the
+// calling thread after the started ones, so the result is the same.
 template <class F>
 void parallel_runs(int64_t items, int workers, F f) {
     std::vector<std::thread> th;
     std::vector<std::exception_ptr> err(static_cast<size_t>(workers));
-    for (int w = 0; w < workers; ++w) {
+    auto run = [&](int w) {
         const int64_t first = items * w / workers, last = items * (w + 1) / workers;
-        th.emplace_back([&, w, first, last]() {
-            try {
-                f(w, first, last);
-            } catch (...) {
-                err[size_t(w)] = std::current_exception();
-            }
-        });
+        try {
+            f(w, first, last);
+        } catch (...) {
+            err[size_t(w)] = std::current_exception();
+        }
+    };
+    int started = 0;
+    try {
+        th.reserve(size_t(workers));
+        for (; started < workers; ++started) th.emplace_back(run, started);
+    } catch (...) {
+        // the std::thread of run `started` was never created
     }
+    for (int w = started; w < workers; ++w) run(w);
     for (auto &t : th) t.join();
     for (auto &e : err)
         if (e) std::rethrow_exception(e);

@@ -50,12 +50,21 @@ def test_every_header_function_is_exported():
     assert set(names) == set(lms._SIGS)
 
 
+# entry points that compute something the paper defines (the others are
+# introspection, errors, teardown, options and the allocation-free variant)
+CITED = ("lms_build_csr", "lms_build_csr_batched", "lms_reorder", "lms_reorder_device",
+         "lms_reorder_with_quality", "lms_permute", "lms_smooth", "lms_sweep", "lms_quality",
+         "lms_quality_batched", "lms_host_vertex_quality", "lms_reuse_profile")
+
+
 def test_header_cites_the_paper_for_each_entry_point():
     text = open(lms.HEADER).read()
-    for fn in ("lms_build_csr", "lms_reorder", "lms_smooth", "lms_quality"):
-        block = text[:text.index(fn + "(")]
+    for fn in CITED:
+        assert fn in lms.header_functions(), fn
+        m = re.search(r"\b" + fn + r"\(", text)
+        block = text[:m.start()]
         comment = block[block.rfind("/*"):]
-        assert re.search(r"(Eq\.|Algorithm|Section)", comment), fn
+        assert re.search(r"(Eq\.|Algorithm|Section|Table|Figure) ?\d", comment), fn
 
 
 def oracle_smoothing_csr(top, new2old):
@@ -89,6 +98,19 @@ def test_csr_fixed_and_colours_match_oracle(name):
     assert np.array_equal(colour, ocol)
     assert info["n_colors"] == ocol.max() + 1
     assert info["max_degree"] == top.degree[top.fixed == 0].max()
+
+
+def test_library_colouring_equals_the_hand_traced_example():
+    with open(os.path.join(HERE, "golden", "colouring_example.json")) as f:
+        g = json.load(f)
+    tri = np.array(g["tri"], dtype=np.int32)
+    M = lms.Mesh.build_csr(g["n"], tri)
+    fx, colour = M.vertex_data()
+    assert colour.tolist() == g["colour"]
+    assert M.info()["n_colors"] == len(g["colour_lists"])
+    # relabelling carries the colours along with the vertices
+    p = M.reorder("random", seed=3)
+    assert M.vertex_data()[1].tolist() == np.array(g["colour"])[p].tolist()
 
 
 @pytest.mark.parametrize("name", sorted(MESHES))
@@ -253,12 +275,13 @@ def test_oversized_triangle_count_is_rejected_before_allocating():
     assert lib.lms_build_csr(3, (1 << 40) + 1, lms._np_ptr(tri), None, ctypes.byref(h)) == 1
 
 
-def test_no_kernel_spills_to_scratch():
+@pytest.mark.parametrize("source", ["lms_device.hip", "lms_reorder.hip"])
+def test_no_kernel_spills_to_scratch(source):
     # every device kernel must keep its arrays in registers: a kernel with
     # private (scratch) memory runs its loads through memory and slows down
     import subprocess
     from paper_1606_00803_amd import build as b
-    src = os.path.join(b.CSRC, "lms_device.hip")
+    src = os.path.join(b.CSRC, source)
     cmd = [b._hipcc(), *b.COMMON, f"--offload-arch={b.ARCH}", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", "-Wno-unused-command-line-argument", "-Rpass-analysis=kernel-resource-usage",
            "--cuda-device-only", "-c", src, "-o", os.devnull]
@@ -266,7 +289,7 @@ def test_no_kernel_spills_to_scratch():
     assert out.returncode == 0, out.stderr[-2000:]
     names = re.findall(r"Function Name: (\S+)", out.stderr)
     scratch = [int(v) for v in re.findall(r"ScratchSize \[bytes/lane\]: (\d+)", out.stderr)]
-    assert len(names) == len(scratch) and len(names) > 50
+    assert len(names) == len(scratch) and len(names) > (50 if source == "lms_device.hip" else 5)
     spilled = [n for n, sc in zip(names, scratch) if sc > 0]
     assert not spilled, spilled
 

@@ -242,6 +242,21 @@ def test_colouring_is_proper_and_complete():
     assert 3 <= col.max() + 1 <= 9
 
 
+def test_colouring_hand_traced_first_fit():
+    # a schedule traced by hand from the first-fit rule in ascending label;
+    # visiting in descending label, or taking one past the largest
+    # neighbour colour, gives another colouring and fails here
+    with open(os.path.join(os.path.dirname(__file__), "golden", "colouring_example.json")) as f:
+        g = json.load(f)
+    top = omesh.topology(g["n"], np.array(g["tri"]))
+    assert top.interior.tolist() == g["free"]
+    col = oord.greedy_colouring(top)
+    assert col.tolist() == g["colour"]
+    assert col.tolist() != g["colour_descending_visit"]
+    ptr, lst = oord.colour_lists(col)
+    assert [lst[ptr[c]:ptr[c + 1]].tolist() for c in range(ptr.size - 1)] == g["colour_lists"]
+
+
 def test_multicolour_equals_dense_colour_product():
     m, top = small_mesh(13, seed=31)
     A = omesh.smoothing_operator_dense(top)
