@@ -218,6 +218,26 @@ lms_status lms_sweep(lms_mesh_t m, const void *sx, const void *sy, void *dx, voi
 lms_status lms_quality(lms_mesh_t m, const void *x, const void *y, lms_precision p,
                        double *q_global, double *q_vertex, void *stream);
 
+/* lms_quality for callers that cannot allocate device memory (code that a
+ * caller captures into a graph, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or allocating routine.  It
+ * computes the global quality only, into device memory, and never waits for
+ * the stream.
+ *   x, y      device [n], current labels (float64 or float32 per p)
+ *   q_global  device float64[1] out: the same value lms_quality returns, from
+ *             the same kernels
+ * Its partial sums live in a library-owned array of 8192 float64 (64 KiB)
+ * that every GPU holds from the library's load until the process ends; every
+ * mesh size fits it.  All calls on one GPU share that array, so calls that
+ * overlap on one GPU (other streams, other threads, other handles) race:
+ * order them.  The handle's mesh arrays must already be on the current
+ * device: after building or reordering a handle, make one other device call
+ * on it (lms_quality, lms_permute, lms_sweep or lms_smooth) first, else the
+ * call fails with LMS_ERR_STATE.  LMS_ERR_ARG for a null pointer or an
+ * unknown precision.  Asynchronous on `stream`. */
+lms_status lms_quality_noalloc(lms_mesh_t m, const void *x, const void *y, lms_precision p,
+                               double *q_global, void *stream);
+
 /* Per-mesh quality of a batched handle (Section 3.2's mesh quality, Algorithm
  * 1's global mean, taken over each mesh's own vertices and triangles):
  * q_mesh host float64[n_mesh] out.  Same arguments and errors as lms_quality;

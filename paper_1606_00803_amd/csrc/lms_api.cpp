@@ -174,6 +174,11 @@ lms_status lms_quality(lms_mesh_t m, const void *x, const void *y, lms_precision
     return guarded([&] { lms::dev_quality(mesh_of(m), x, y, p, q_global, q_vertex, nullptr, stream); });
 }
 
+lms_status lms_quality_noalloc(lms_mesh_t m, const void *x, const void *y, lms_precision p, double *q_global,
+                               void *stream) {
+    return guarded([&] { lms::dev_quality_noalloc(mesh_of(m), x, y, p, q_global, stream); });
+}
+
 lms_status lms_quality_batched(lms_mesh_t m, const void *x, const void *y, lms_precision p, double *q_mesh,
                                void *stream) {
     return guarded([&] {

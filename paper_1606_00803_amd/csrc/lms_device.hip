@@ -14,11 +14,17 @@
 #include <cstring>
 #include <deque>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "lms_internal.hpp"
 #include "lms_kernels.hpp"
+
+// Scratch of lms_quality_noalloc (see dev_quality_noalloc below): 8192
+// partial sums, 64 KiB on every GPU the library runs on.
+constexpr int kScratchDoubles = 8192;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace lms {
 
@@ -2140,6 +2146,82 @@ void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double 
         HIP_CHECK(hipMemcpyAsync(q_global, d.qout, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
     }
+    end_call(d, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free quality (lms_quality_noalloc)
+//
+// The per-block partial sums of the quality pass live in `scratch`, a
+// file-scope array of which every GPU holds its own copy from the library's
+// load until the process ends.  In host code the array's name only stands for
+// the symbol: its device address on the current GPU comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch.  Calls on
+// one GPU share the array (and keep its last contents), so calls that overlap
+// on one GPU race.  Nothing needs clearing: a pass writes every partial the
+// reduction after it reads.
+
+namespace {
+
+static_assert(kScratchDoubles >= kQualMaxBlocks, "the scratch array holds every partial sum");
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch;  // device address of `scratch`, per device (nullptr: not looked up)
+
+double *scratch_on_current_device() {
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch.size() <= size_t(dev)) g_scratch.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch[size_t(dev)]) {
+        void *p = nullptr;
+        HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(LMS_ERR_HIP, "hipGetSymbolAddress returned no address for the quality scratch array");
+        g_scratch[size_t(dev)] = static_cast<double *>(p);
+    }
+    return g_scratch[size_t(dev)];
+}
+
+}  // namespace
+
+void dev_quality_noalloc(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global_dev,
+                         void *stream) {
+    check_precision(p);
+    if (!x || !y || !q_global_dev) fail(LMS_ERR_ARG, "null device pointer");
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    // the handle's device arrays must already be current: uploading them
+    // would allocate
+    if (!M.dev || M.dev->device != dev || M.dev->version != M.version)
+        fail(LMS_ERR_STATE,
+             "the handle's mesh arrays are not on the current device: make one device call on this handle "
+             "(lms_quality, lms_permute, lms_sweep or lms_smooth) after the last reorder first");
+    const int blocks = quality_blocks(M.T);
+    if (blocks > kScratchDoubles)
+        fail(LMS_ERR_ARG, "the quality pass needs " + std::to_string(blocks) + " partial sums; the scratch array holds " +
+                              std::to_string(kScratchDoubles));
+    double *part = scratch_on_current_device();
+    DeviceState &d = *M.dev;
+    hipStream_t s = as_stream(stream);
+    begin_call(d, s);
+    if (p == LMS_FP64) {
+        const double *xd = static_cast<const double *>(x), *yd = static_cast<const double *>(y);
+        if (d.trec)
+            k_quality<double, kQualBS><<<blocks, kQualBS, 0, s>>>(d.trec, xd, yd, nullptr, M.T, part, nullptr, nullptr);
+        else
+            k_quality_wide<double, kQualBS><<<blocks, kQualBS, 0, s>>>(d.ta, d.tb, d.tc, d.tw, xd, yd, nullptr, M.T,
+                                                                      part, nullptr, nullptr);
+    } else {
+        const float *xf = static_cast<const float *>(x), *yf = static_cast<const float *>(y);
+        if (d.trec)
+            k_quality<float, kQualBS><<<blocks, kQualBS, 0, s>>>(d.trec, xf, yf, nullptr, M.T, part, nullptr, nullptr);
+        else
+            k_quality_wide<float, kQualBS><<<blocks, kQualBS, 0, s>>>(d.ta, d.tb, d.tc, d.tw, xf, yf, nullptr, M.T,
+                                                                     part, nullptr, nullptr);
+    }
+    launch_check();
+    k_reduce_out<<<1, 256, 0, s>>>(part, blocks, 1.0 / double(M.n), q_global_dev);
+    launch_check();
     end_call(d, s);
 }
 

@@ -226,5 +226,7 @@ void dev_reorder(Mesh &M, lms_ordering kind, const std::vector<int32_t> &given, 
                  std::vector<int32_t> &new2old_out);
 void dev_quality(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global,
                  double *q_vertex, double *q_mesh, void *stream);
+void dev_quality_noalloc(Mesh &M, const void *x, const void *y, lms_precision p, double *q_global_dev,
+                         void *stream);
 
 }  // namespace lms

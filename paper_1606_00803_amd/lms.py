@@ -75,6 +75,7 @@ _SIGS = {
     "lms_sweep": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "lms_quality": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp]),
     "lms_quality_batched": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
+    "lms_quality_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "lms_sweep_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_char_p, _i32]),
     "lms_destroy": (ctypes.c_int, [_vp]),
     "lms_last_error": (ctypes.c_char_p, []),
@@ -340,6 +341,17 @@ class Mesh:
         out = ctypes.c_double()
         _check(load().lms_quality(self.handle, a, b, p, ctypes.byref(out), qv, _stream()))
         return out.value
+
+    def quality_noalloc(self, x, y, q_out) -> None:
+        """lms_quality_noalloc: Q into the float64 device tensor q_out[0],
+        asynchronously on the current stream."""
+        n = self.n
+        a, p = _dev(x, n, "x")
+        b, _ = _dev(y, n, "y")
+        import torch
+        if q_out.dtype != torch.float64 or not q_out.is_cuda or q_out.numel() < 1:
+            raise TypeError("q_out must be a float64 device tensor of at least one element")
+        _check(load().lms_quality_noalloc(self.handle, a, b, p, q_out.data_ptr(), _stream()))
 
     def sweep_config(self, precision="f64") -> str:
         buf = ctypes.create_string_buffer(8192)
