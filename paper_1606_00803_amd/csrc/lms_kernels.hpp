@@ -335,6 +335,60 @@ struct Vec2Of<float> {
 template <typename T>
 using vec2_t = typename Vec2Of<T>::type;
 
+// Sum over a row's neighbours in LDS, in slot order (the row's ascending
+// neighbour order), from 0, and their count.  slot(q) is the row's q-th
+// 16-bit slot, 0xFFFF past its end.  Each read sits behind its own branch and
+// waits for its value: the reads of the other waves on the SIMD cover that
+// wait.  A form with all of a row's reads in flight at once needed ~20 more
+// registers, which let one 1024-thread workgroup per CU run instead of two,
+// and measured slower on every ordering.
+template <typename T, int W, class Slot>
+__device__ __forceinline__ int lds_row_sum(const vec2_t<T> *sp, Slot slot, T &ax, T &ay) {
+    T sx = T(0), sy = T(0);
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        const uint32_t id = slot(q);
+        if (id != 0xFFFFu) {
+            const vec2_t<T> p = sp[id];
+            sx += p.x;
+            sy += p.y;
+            ++c;
+        }
+    }
+    ax = sx;
+    ay = sy;
+    return c;
+}
+
+// The same for slots packed two per word (slot 2q in the low half of word q).
+template <typename T, int W>
+__device__ __forceinline__ int lds_row_sum_words(const vec2_t<T> *sp, const uint32_t (&wd)[W / 2], T &ax, T &ay) {
+    return lds_row_sum<T, W>(sp, [&](int q) { return (wd[q / 2] >> (16 * (q % 2))) & 0xFFFFu; }, ax, ay);
+}
+
+// Stage rows ids[0..cnt) of src into sp[base + j], four per thread per step:
+// the ids, then the coordinates, each as four loads in flight together.  An
+// index past cnt is clamped to cnt-1, so that lane loads and stores entry
+// cnt-1's own value again: no branch holds a load back.
+template <typename T, int BS>
+__device__ __forceinline__ void stage_rows(const int32_t *__restrict__ ids, int32_t cnt,
+                                           const vec2_t<T> *__restrict__ src, vec2_t<T> *sp, int32_t base,
+                                           int tid) {
+    for (int32_t j0 = tid; j0 < cnt; j0 += 4 * BS) {
+        int32_t j[4], g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) j[q] = min(j0 + q * BS, cnt - 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = ids[j[q]];
+        vec2_t<T> h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = src[g[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sp[base + j[q]] = h[q];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack(const T *__restrict__ x, const T *__restrict__ y,
                                               vec2_t<T> *__restrict__ a, vec2_t<T> *__restrict__ b, int32_t n) {
@@ -518,41 +572,10 @@ __global__ __launch_bounds__(TS) void k_jacobi_halo(const int32_t *__restrict__ 
     load_row_slots<W>(lidx + (int64_t(tile) * TS + tid) * W, li);
     if (v < n) stage[tid] = src[v];
     const int32_t hb = halo_ptr[tile], he = halo_ptr[tile + 1];
-    for (int32_t j0 = hb + tid; j0 < he; j0 += 4 * TS) {
-        int32_t g[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] = j0 + q * TS < he ? halo[j0 + q * TS] : -1;
-        T hx[4], hy[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            hx[q] = T(0);
-            hy[q] = T(0);
-            if (g[q] >= 0) {
-                const vec2_t<T> h = src[g[q]];
-                hx[q] = h.x;
-                hy[q] = h.y;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (g[q] >= 0) {
-                vec2_t<T> h;
-                h.x = hx[q];
-                h.y = hy[q];
-                stage[TS + (j0 + q * TS - hb)] = h;
-            }
-    }
+    stage_rows<T, TS>(halo + hb, he - hb, src, stage, TS, tid);
     __syncthreads();
-    T ax = T(0), ay = T(0);
-    int c = 0;
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-        if (li[k] != 0xFFFF) {
-            const vec2_t<T> p = stage[li[k]];
-            ax += p.x;
-            ay += p.y;
-            ++c;
-        }
+    T ax, ay;
+    const int c = lds_row_sum<T, W>(stage, [&](int q) { return uint32_t(li[q]); }, ax, ay);
     if (c > 0) {
         vec2_t<T> o;
         o.x = ax / T(c);
@@ -681,31 +704,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     if constexpr (!G)
         for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
     const int32_t g0 = G ? 0 : nown;  // first staged row read through the list
-    const int32_t nh = nload - g0;
-    for (int32_t j0 = tid; j0 < nh; j0 += 4 * BS) {
-        int32_t g[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] = j0 + q * BS < nh ? halo[hb + j0 + q * BS] : -1;
-        T hx[4], hy[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            hx[q] = T(0);
-            hy[q] = T(0);
-            if (g[q] >= 0) {
-                const vec2_t<T> h = src[g[q]];
-                hx[q] = h.x;
-                hy[q] = h.y;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (g[q] >= 0) {
-                vec2_t<T> h;
-                h.x = hx[q];
-                h.y = hy[q];
-                sp[g0 + j0 + q * BS] = h;
-            }
-    }
+    stage_rows<T, BS>(halo + hb, nload - g0, src, sp, g0, tid);
     __syncthreads();
     const int32_t passes = QUAL && k == 0 ? 1 : k;
     for (int32_t j = 1; j <= passes; ++j) {
@@ -743,18 +742,8 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             const int32_t i = tid + BS * r;
             if (BS * r >= m) continue;  // the same for the whole workgroup
             if (i >= m) continue;
-            T ax = T(0), ay = T(0);
-            int c = 0;
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                const uint32_t id = (wd[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
-                if (id != 0xFFFFu) {
-                    const vec2_t<T> p = sp[id];
-                    ax += p.x;
-                    ay += p.y;
-                    ++c;
-                }
-            }
+            T ax, ay;
+            const int c = lds_row_sum_words<T, W>(sp, wd[r], ax, ay);
             w[r] = c > 0;
             if (c > 0) {
                 o[r].x = ax / T(c);
@@ -762,10 +751,14 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             }
         }
         if (j == k) {
+            int32_t vid[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r)  // ids of the own rows, loads in flight together
+                vid[r] = G ? halo[hb + min(tid + BS * r, nown - 1)] : b + tid + BS * r;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (w[r]) {
-                    const int32_t v = G ? halo[hb + tid + BS * r] : b + tid + BS * r;
+                    const int32_t v = vid[r];
                     if (ox) {
                         ox[v] = o[r].x;
                         oy[v] = o[r].y;
@@ -827,18 +820,8 @@ __global__ __launch_bounds__(256) void k_small_meshes(const int64_t *__restrict_
         for (int r = 0; r < R; ++r) {
             w[r] = false;
             if (256 * r >= nv) continue;  // the same for the whole workgroup
-            T ax = T(0), ay = T(0);
-            int c = 0;
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                const uint32_t id = (slot[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
-                if (id != 0xFFFFu) {
-                    const vec2_t<T> p = sp[id];
-                    ax += p.x;
-                    ay += p.y;
-                    ++c;
-                }
-            }
+            T ax, ay;
+            const int c = lds_row_sum_words<T, W>(sp, slot[r], ax, ay);
             w[r] = c > 0;
             o[r].x = w[r] ? ax / T(c) : T(0);
             o[r].y = w[r] ? ay / T(c) : T(0);
@@ -975,30 +958,7 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
     }
     if constexpr (!G)
         for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
-    for (int32_t j0 = tid; j0 < nh; j0 += 4 * BS) {
-        int32_t g[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] = j0 + q * BS < nh ? halo[hb + j0 + q * BS] : -1;
-        T hx[4], hy[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            hx[q] = T(0);
-            hy[q] = T(0);
-            if (g[q] >= 0) {
-                const vec2_t<T> h = src[g[q]];
-                hx[q] = h.x;
-                hy[q] = h.y;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (g[q] >= 0) {
-                vec2_t<T> h;
-                h.x = hx[q];
-                h.y = hy[q];
-                sp[g0 + j0 + q * BS] = h;
-            }
-    }
+    stage_rows<T, BS>(halo + hb, nh, src, sp, g0, tid);
     __syncthreads();
     if constexpr (QUAL) {
         // quality of the source state: the tile's triangles, from LDS
@@ -1026,18 +986,8 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
                 if (colr[r] != c) continue;
                 if constexpr (KP > 1)
                     if (!((msk[r] >> (t - 1)) & 1u)) continue;
-                T ax = T(0), ay = T(0);
-                int cnt = 0;
-#pragma unroll
-                for (int q = 0; q < W; ++q) {
-                    const uint32_t id = (wd[r][q / 2] >> (16 * (q % 2))) & 0xFFFFu;
-                    if (id != 0xFFFFu) {
-                        const vec2_t<T> p = sp[id];
-                        ax += p.x;
-                        ay += p.y;
-                        ++cnt;
-                    }
-                }
+                T ax, ay;
+                const int cnt = lds_row_sum_words<T, W>(sp, wd[r], ax, ay);
                 if (cnt > 0) {
                     vec2_t<T> o;
                     o.x = ax / T(cnt);
@@ -1066,7 +1016,26 @@ __device__ __forceinline__ double tri_quality(double xa, double ya, double xb, d
     const double e2 = dx * dx + dy * dy;
     const double mn = fmin(fmin(e0, e1), e2);
     const double mx = fmax(fmax(e0, e1), e2);
-    return mx > 0.0 ? sqrt(mn) / sqrt(mx) : 0.0;
+    // q = sqrt(mn / mx) in [0, 1]: 1/mx from the hardware estimate and two
+    // Newton steps, then the square root of the ratio from the hardware
+    // reciprocal-square-root estimate and a coupled Newton refinement of
+    // sqrt and 1/(2 sqrt); a few units in the last place from the correctly
+    // rounded sqrt(mn) / sqrt(mx).  Outside the range where the estimates
+    // are exact enough (tiny or huge squared lengths), the rounded operations.
+    if (!(mx > 0.0)) return 0.0;
+    if (mx < 0x1p-900 || mx > 0x1p900 || mn < 0x1p-900) return sqrt(mn) / sqrt(mx);
+    double r = __builtin_amdgcn_rcp(mx);
+    r = fma(r, fma(-mx, r, 1.0), r);
+    r = fma(r, fma(-mx, r, 1.0), r);
+    const double s = mn * r;
+    if (s < 0x1p-1000) return sqrt(mn) / sqrt(mx);
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, s);
+    return fma(d, h, g);
 }
 
 // Coordinates of vertex i from structure-of-arrays x/y, or from the

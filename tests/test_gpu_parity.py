@@ -263,6 +263,25 @@ def test_quality_parity(kind, prec):
     assert abs(qm[0] - Q) <= 1e-12
 
 
+@pytest.mark.parametrize("scale", [1e-150, 1e-10, 1.0, 1e10, 1e150])
+def test_quality_at_extreme_scales_and_near_degenerate_triangles(scale):
+    # the device's q_t takes the hardware estimates with Newton steps inside
+    # the range where they are exact enough and the rounded operations
+    # outside it: both ranges, and slivers, against the oracle (Section 3.2)
+    torch = torch_mod()
+    from paper_1606_00803_amd import lms
+    m = meshgen.jittered_grid(40, seed=17)
+    xy = m.xy.copy()
+    xy[41] = xy[1] + np.array([1e-9, 1e-9])      # slivers next to vertex 1: mn / mx ~ 1e-14
+    xy *= scale
+    x, y = np.ascontiguousarray(xy[:, 0]), np.ascontiguousarray(xy[:, 1])
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    qdev = torch.empty(m.n, dtype=torch.float64, device="cuda")
+    Q = M.quality(to_dev(x, torch.float64), to_dev(y, torch.float64), q_vertex=qdev)
+    assert abs(Q - oq.global_quality(x, y, m.tri, m.n)) <= 1e-12
+    assert np.max(np.abs(qdev.cpu().numpy() - oq.vertex_quality(x, y, m.tri, m.n))) <= 1e-14
+
+
 @pytest.mark.parametrize("kind", ["rdr", "random"])
 def test_fp32_error_vs_fp64_oracle(kind):
     torch = torch_mod()
