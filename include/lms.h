@@ -324,6 +324,24 @@ typedef struct lms_reuse_stats {
 lms_status lms_reuse_profile(lms_mesh_t m, const double *fractions, int32_t nfrac, int64_t *quantiles,
                              int32_t line_bytes, int32_t record_bytes, lms_reuse_stats *stats);
 
+/* lms_reuse_profile over a chosen access trace (Section 2's reuse distance;
+ * Table 2 profiles its own code's full run, whose trace it does not spell
+ * out).
+ *   trace  LMS_TRACE_SWEEP (0): the trace of lms_reuse_profile;
+ *          LMS_TRACE_ALGORITHM1 (1): Algorithm 1's loop body, the smoothing
+ *          of V[i] (the vertex, then its neighbours in ascending current
+ *          label) followed by the update of the global quality: every
+ *          triangle containing the vertex, in ascending current triangle
+ *          index, as its three corners in ascending label and then the
+ *          triangle's quality record.  Items are vertex labels 0..n-1 and
+ *          triangle records n..n+T-1.
+ * Other arguments, outputs and errors as lms_reuse_profile (LMS_ERR_ARG for
+ * an unknown trace); lines_per_wave counts the neighbour reads only. */
+typedef enum { LMS_TRACE_SWEEP = 0, LMS_TRACE_ALGORITHM1 = 1 } lms_trace_kind;
+lms_status lms_reuse_profile_trace(lms_mesh_t m, int32_t trace, const double *fractions, int32_t nfrac,
+                                   int64_t *quantiles, int32_t line_bytes, int32_t record_bytes,
+                                   lms_reuse_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,6 +10,9 @@ spell the trace out):
   ascending current label, the vertex itself and then its neighbours in
   ascending current label.  Items are current labels (storage positions);
   fixed vertices are read as neighbours only.
+* The second trace follows Algorithm 1's loop body, which smooths V[i] and
+  then updates the global quality: after each vertex's neighbours come the
+  triangles containing it (their corners, then their quality record).
 * The reuse distance of an access to x is the number of distinct items
   accessed strictly between it and the previous access to x.  A first access
   has none; it is counted apart as cold.
@@ -46,6 +49,50 @@ def sweep_trace(top: Topology, new2old) -> np.ndarray:
         out.append(k)
         nb = sorted(int(old2new[u]) for u in top.neighbours(v))
         out.extend(nb)
+    return np.asarray(out, dtype=np.int64)
+
+
+def triangle_rank(tri, new2old) -> np.ndarray:
+    """Storage index of each input triangle under an ordering: triangles sorted
+    by (smallest new label of a corner, input index)."""
+    tri = np.asarray(tri, dtype=np.int64).reshape(-1, 3)
+    new2old = np.asarray(new2old, dtype=np.int64)
+    old2new = np.empty(new2old.size, dtype=np.int64)
+    old2new[new2old] = np.arange(new2old.size)
+    key = old2new[tri].min(axis=1)
+    order = sorted(range(tri.shape[0]), key=lambda i: (int(key[i]), i))
+    rank = np.empty(tri.shape[0], dtype=np.int64)
+    rank[np.asarray(order, dtype=np.int64)] = np.arange(tri.shape[0])
+    return rank
+
+
+def algorithm1_trace(top: Topology, new2old) -> np.ndarray:
+    """Access trace of Algorithm 1's loop body over the free vertices in
+    storage order: smoothing V[i] reads the vertex and its neighbours (as in
+    sweep_trace); updating the global quality then recomputes every triangle
+    containing it, in ascending storage index, reading its three corners in
+    ascending current label and writing the triangle's quality record.  Items
+    are current labels 0..n-1 and triangle records n + storage index."""
+    new2old = np.asarray(new2old, dtype=np.int64)
+    n = top.n
+    old2new = np.empty(n, dtype=np.int64)
+    old2new[new2old] = np.arange(n)
+    tri = np.asarray(top.tri, dtype=np.int64).reshape(-1, 3)
+    rank = triangle_rank(tri, new2old)
+    of_vertex = [[] for _ in range(n)]          # input vertex -> its triangles (input indices)
+    for i, (a, b, c) in enumerate(tri.tolist()):
+        for v in (a, b, c):
+            of_vertex[v].append(i)
+    out = []
+    for k in range(n):
+        v = int(new2old[k])
+        if top.fixed[v]:
+            continue
+        out.append(k)
+        out.extend(sorted(int(old2new[u]) for u in top.neighbours(v)))
+        for i in sorted(of_vertex[v], key=lambda i: int(rank[i])):
+            out.extend(sorted(int(old2new[u]) for u in tri[i]))
+            out.append(n + int(rank[i]))
     return np.asarray(out, dtype=np.int64)
 
 
@@ -119,8 +166,8 @@ def wave_line_spans(top: Topology, new2old, line_bytes: int = 128, record_bytes:
 
 
 def profile(top: Topology, new2old, fractions=(0.5, 0.75, 0.9, 1.0), line_bytes: int = 128,
-            record_bytes: int = 16) -> dict:
-    tr = sweep_trace(top, new2old)
+            record_bytes: int = 16, trace: str = "sweep") -> dict:
+    tr = sweep_trace(top, new2old) if trace == "sweep" else algorithm1_trace(top, new2old)
     d, cold = reuse_distances(tr)
     spans = wave_line_spans(top, new2old, line_bytes, record_bytes)
     return dict(accesses=int(tr.size), cold=cold,

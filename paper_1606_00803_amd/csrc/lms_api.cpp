@@ -255,7 +255,16 @@ lms_status lms_reuse_profile(lms_mesh_t m, const double *fractions, int32_t nfra
                              int32_t line_bytes, int32_t record_bytes, lms_reuse_stats *stats) {
     return guarded([&] {
         if (!stats) lms::fail(LMS_ERR_ARG, "null stats");
-        lms::reuse_profile(mesh_of(m), fractions, nfrac, quantiles, line_bytes, record_bytes, *stats);
+        lms::reuse_profile(mesh_of(m), 0, fractions, nfrac, quantiles, line_bytes, record_bytes, *stats);
+    });
+}
+
+lms_status lms_reuse_profile_trace(lms_mesh_t m, int32_t trace, const double *fractions, int32_t nfrac,
+                                   int64_t *quantiles, int32_t line_bytes, int32_t record_bytes,
+                                   lms_reuse_stats *stats) {
+    return guarded([&] {
+        if (!stats) lms::fail(LMS_ERR_ARG, "null stats");
+        lms::reuse_profile(mesh_of(m), trace, fractions, nfrac, quantiles, line_bytes, record_bytes, *stats);
     });
 }
 

@@ -1448,20 +1448,47 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
     return M.mc_plans.back();
 }
 
-// Locality profile of the current ordering: reuse distances of the sweep's
-// access trace (a Fenwick tree over trace positions marks each item's last
-// access; the distinct items since then are the marks after it), exact
-// quantiles from their histogram, and cache-line spans per wavefront.
-void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,
-                   int32_t record_bytes, lms_reuse_stats &out) {
+// Locality profile of the current ordering: reuse distances of an access
+// trace (a Fenwick tree over trace positions marks each item's last access;
+// the distinct items since then are the marks after it), exact quantiles from
+// their histogram, and cache-line spans per wavefront.
+//
+// trace 0 (one sweep of Eq. 1): every free vertex in ascending current label,
+// then its neighbours in ascending label.  trace 1 (Algorithm 1's loop body,
+// the smoothing of V[i] followed by the update of the global quality): the
+// same, and after each vertex's neighbours, every triangle containing it in
+// ascending current triangle index, as its three corners in ascending label
+// followed by the triangle's own quality record.  Items are vertex labels
+// 0..n-1 and triangle records n..n+T-1.
+void reuse_profile(const Mesh &M, int32_t trace, const double *fractions, int32_t nfrac, int64_t *quantiles,
+                   int32_t line_bytes, int32_t record_bytes, lms_reuse_stats &out) {
     if (nfrac < 0 || (nfrac > 0 && (!fractions || !quantiles)) || line_bytes <= 0 || record_bytes <= 0)
         fail(LMS_ERR_ARG, "reuse profile: bad fractions or sizes");
+    if (trace != 0 && trace != 1) fail(LMS_ERR_ARG, "reuse profile: unknown trace");
     for (int32_t i = 0; i < nfrac; ++i)
         if (!(fractions[i] >= 0.0 && fractions[i] <= 1.0)) fail(LMS_ERR_ARG, "reuse profile: fraction outside [0, 1]");
     const int32_t n = M.n;
+    const int64_t items = trace == 1 ? int64_t(n) + M.T : int64_t(n);
+    // the trace, in order, to an access function
+    auto walk = [&](auto &&emit) {
+        for (int32_t v = 0; v < n; ++v) {
+            if (M.fixed[size_t(v)]) continue;
+            emit(int64_t(v));
+            for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) emit(int64_t(M.col[size_t(j)]));
+            if (trace == 1)
+                for (int32_t e = M.vt_ptr[v]; e < M.vt_ptr[v + 1]; ++e) {
+                    const int32_t t = M.vt[size_t(e)];
+                    int32_t c[3] = {M.ta[size_t(t)], M.tb[size_t(t)], M.tc[size_t(t)]};
+                    std::sort(c, c + 3);
+                    emit(int64_t(c[0]));
+                    emit(int64_t(c[1]));
+                    emit(int64_t(c[2]));
+                    emit(int64_t(n) + t);
+                }
+        }
+    };
     int64_t L = 0;
-    for (int32_t v = 0; v < n; ++v)
-        if (!M.fixed[size_t(v)]) L += 1 + (M.row_ptr[v + 1] - M.row_ptr[v]);
+    walk([&](int64_t) { ++L; });
     if (L >= (int64_t(1) << 31)) fail(LMS_ERR_STATE, "reuse profile: trace too long");
     std::vector<int32_t> fen(size_t(L) + 1, 0);  // 1-based Fenwick tree over trace positions
     auto add = [&](int64_t i, int32_t d) {
@@ -1472,11 +1499,11 @@ void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_
         for (; i > 0; i -= i & -i) acc += fen[size_t(i)];
         return acc;
     };
-    std::vector<int64_t> last(size_t(n), -1);
-    std::vector<int64_t> hist(size_t(n) + 1, 0);
+    std::vector<int64_t> last(size_t(items), -1);
+    std::vector<int64_t> hist(size_t(items) + 1, 0);
     int64_t t = 0, cold = 0, dmax = 0;
     double dsum = 0.0;
-    auto access = [&](int32_t x) {
+    walk([&](int64_t x) {
         const int64_t p = last[size_t(x)];
         if (p < 0) {
             ++cold;
@@ -1490,19 +1517,14 @@ void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_
         add(t, 1);
         last[size_t(x)] = t;
         ++t;
-    };
-    for (int32_t v = 0; v < n; ++v) {
-        if (M.fixed[size_t(v)]) continue;
-        access(v);
-        for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) access(M.col[size_t(j)]);
-    }
+    });
     const int64_t total = L - cold;
     for (int32_t i = 0; i < nfrac; ++i) {
         int64_t q = 0;
         if (total > 0) {
             const int64_t need = std::max<int64_t>(1, int64_t(std::ceil(fractions[i] * double(total) - 1e-12)));
             int64_t cum = 0;
-            for (q = 0; q <= n; ++q) {
+            for (q = 0; q <= items; ++q) {
                 cum += hist[size_t(q)];
                 if (cum >= need) break;
             }

@@ -210,8 +210,8 @@ const Mesh::MCPlan &mc_plan(Mesh &M, int32_t ts, int32_t l_cap, int32_t u_cap, b
                             int32_t k = 1);
 const Mesh::Patches &patch_set(Mesh &M, int32_t ts);
 void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P);
-void reuse_profile(const Mesh &M, const double *fractions, int32_t nfrac, int64_t *quantiles, int32_t line_bytes,
-                   int32_t record_bytes, lms_reuse_stats &out);
+void reuse_profile(const Mesh &M, int32_t trace, const double *fractions, int32_t nfrac, int64_t *quantiles,
+                   int32_t line_bytes, int32_t record_bytes, lms_reuse_stats &out);
 
 // ---- device runtime (lms_device.hip) ----
 void dev_permute(Mesh &M, const void *sx, const void *sy, void *dx, void *dy,

@@ -27,6 +27,8 @@ STOP_MAX_ITERS, STOP_TOL, STOP_GOAL = 0, 1, 2
 ORDERINGS = {"ori": ORI, "bfs": BFS, "rdr": RDR, "random": RANDOM}
 SCHEMES = {"jacobi": JACOBI, "multicolor": MULTICOLOR}
 STOP_NAMES = {STOP_MAX_ITERS: "max_iters", STOP_TOL: "tol", STOP_GOAL: "goal"}
+TRACE_SWEEP, TRACE_ALGORITHM1 = 0, 1
+TRACES = {"sweep": TRACE_SWEEP, "algorithm1": TRACE_ALGORITHM1}
 STATUS_NAMES = {0: "LMS_OK", 1: "LMS_ERR_ARG", 2: "LMS_ERR_MESH", 3: "LMS_ERR_ALLOC",
                 4: "LMS_ERR_HIP", 5: "LMS_ERR_STATE"}
 
@@ -86,6 +88,7 @@ _SIGS = {
     "lms_host_vertex_quality": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "lms_reorder_device": (ctypes.c_int, [_vp, _i32, _u64, _vp, _vp, _vp, _vp]),
     "lms_reuse_profile": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i32, _i32, ctypes.POINTER(ReuseStats)]),
+    "lms_reuse_profile_trace": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp, _i32, _i32, ctypes.POINTER(ReuseStats)]),
 }
 
 
@@ -273,14 +276,21 @@ class Mesh:
         return q
 
     def reuse_profile(self, fractions=(0.5, 0.75, 0.9, 1.0), line_bytes: int = 128,
-                      record_bytes: int = 16) -> dict:
-        """Locality of the current ordering (reuse-distance quantiles of one
-        sweep's access trace, cache-line spans per wavefront); host only."""
+                      record_bytes: int = 16, trace: str = "sweep") -> dict:
+        """Locality of the current ordering (reuse-distance quantiles of an
+        access trace: "sweep", one sweep of Eq. 1, or "algorithm1", the sweep
+        with Algorithm 1's quality upkeep; cache-line spans per wavefront);
+        host only."""
         f = np.ascontiguousarray(fractions, dtype=np.float64)
         q = np.zeros(f.size, dtype=np.int64)
         st = ReuseStats()
-        _check(load().lms_reuse_profile(self.handle, _np_ptr(f), int(f.size), _np_ptr(q), int(line_bytes),
-                                        int(record_bytes), ctypes.byref(st)))
+        if trace == "sweep":
+            _check(load().lms_reuse_profile(self.handle, _np_ptr(f), int(f.size), _np_ptr(q), int(line_bytes),
+                                            int(record_bytes), ctypes.byref(st)))
+        else:
+            kind = TRACES[trace] if isinstance(trace, str) else int(trace)
+            _check(load().lms_reuse_profile_trace(self.handle, kind, _np_ptr(f), int(f.size), _np_ptr(q),
+                                                  int(line_bytes), int(record_bytes), ctypes.byref(st)))
         return dict(accesses=st.accesses, cold=st.cold, quantiles=[int(v) for v in q], mean=st.mean,
                     max=st.max, lines_per_wave=st.lines_per_wave, max_lines_per_wave=st.max_lines_per_wave)
 

@@ -538,6 +538,26 @@ def test_reuse_distance_hand_example():
         assert d.tolist() == [2, 2, 0] and cold == 3
 
 
+def test_algorithm1_trace_hand_traced_on_a_wheel():
+    # centre 0 (free) with rim 1, 2, 3 (fixed); triangles (0,1,2), (0,2,3),
+    # (0,3,1), all with smallest corner 0, so they keep their input order.
+    # Traced by hand: the centre, its neighbours; then per triangle its sorted
+    # corners and its quality record (items 4, 5, 6).
+    from oracle import mesh as omesh
+    from oracle import reuse as ore
+    tri = np.array([[0, 1, 2], [0, 2, 3], [0, 3, 1]])
+    top = omesh.topology(4, tri)
+    assert top.fixed.tolist() == [0, 1, 1, 1]
+    tr = ore.algorithm1_trace(top, np.arange(4))
+    assert tr.tolist() == [0, 1, 2, 3, 0, 1, 2, 4, 0, 2, 3, 5, 0, 1, 3, 6]
+    for f in (ore.reuse_distances, ore.reuse_distances_brute):
+        d, cold = f(tr)
+        assert d.tolist() == [3, 3, 3, 3, 2, 4, 3, 5, 3] and cold == 7
+    # under the labels reversed, the triangles sort by their smallest new label
+    p = np.array([3, 2, 1, 0])               # new label k holds input vertex p[k]
+    assert ore.triangle_rank(tri, p).tolist() == [2, 0, 1]  # keys (1,0), (0,1), (0,2)
+
+
 def test_reuse_distance_stack_matches_definition_on_random_traces():
     from oracle import reuse as ore
     rng = np.random.default_rng(11)
