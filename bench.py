@@ -38,7 +38,8 @@ ORDER_NAMES = ["ori", "bfs", "rdr", "random"]
 RANDOM_SEED = 1002
 METRIC = "vertex-updates/sec and % HBM roofline per ordering (ORI/BFS/RDR/random), FP64 vs FP32"
 COUNTERS = {"ocean": os.path.join(ROOT, "profiles", "sweep_ocean_rdr_f64_counters.md"),
-            "graded16m": os.path.join(ROOT, "profiles", "sweep_graded16m_counters.md")}
+            "graded16m": os.path.join(ROOT, "profiles", "sweep_graded16m_counters.md"),
+            "batch512": os.path.join(ROOT, "profiles", "sweep_batch512_counters.md")}
 # the kernels' source: counter summaries taken on other kernel code are not used
 DEVICE_SRC = os.path.join(ROOT, "paper_1606_00803_amd", "csrc", "lms_kernels.hpp")
 
@@ -206,49 +207,111 @@ def marginal_launch_us(torch, M, x, y, tx, ty, scheme, reps=5):
     return (ms[k2] - ms[k1]) * 1e3 / (reps * (k2 - k1) / k)
 
 
-def cpu_baseline(m, sweeps, budget_s=10.0, one_core_s=3.0):
-    from oracle import mesh as omesh
-    from oracle import smooth as osm
-    top = omesh.topology(m.n, m.tri)
+# The GPU machine gives one process a share of 16 host threads, whatever the
+# affinity mask shows; the oracle's OpenMP schedule uses at most that many.
+HOST_THREAD_SHARE = 16
+
+
+def host_cores():
+    """(threads the oracle uses, logical CPUs in the affinity mask, logical CPUs of the host)."""
     try:
-        cores = len(os.sched_getaffinity(0))
+        visible = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    reps = 0
-    w0 = time.perf_counter()
-    while reps < 1 or time.perf_counter() - w0 < budget_s:
-        osm.jacobi(top, m.x, m.y, sweeps, threads=cores)
-        reps += 1
-    wall = time.perf_counter() - w0
-    free = int((top.fixed == 0).sum())
-    out = dict(value=free * sweeps * reps / wall, unit="vertex-updates/s", cores=cores, kind="oracle",
-               sample=f"the full workload ({m.n} vertices, {sweeps} float64 Jacobi sweeps, ORI labels) "
-                      f"repeated {reps} times, OpenMP static schedule over {cores} threads",
-               host_cpu=host_cpu_model())
-    if one_core_s > 0:
-        # the same sweeps on one thread: runs of k1 sweeps (fewer than the
-        # workload's on a large mesh) repeated for about one_core_s seconds
-        k1 = max(1, min(sweeps, int(one_core_s * 1e8 / max(1, free))))
-        reps1 = 0
-        w0 = time.perf_counter()
-        while reps1 < 1 or time.perf_counter() - w0 < one_core_s:
-            osm.jacobi(top, m.x, m.y, k1, threads=1)
-            reps1 += 1
-        out["one_core_value"] = free * k1 * reps1 / (time.perf_counter() - w0)
-        out["one_core_sample"] = f"{k1} float64 Jacobi sweeps of the same mesh on one thread, {reps1} times"
-    return out, top
+        visible = os.cpu_count() or 1
+    return max(1, min(visible, HOST_THREAD_SHARE)), visible, os.cpu_count() or visible
+
+
+def relabelled(m, top, new2old):
+    """The oracle's view of mesh m under an ordering: input vertex new2old[k]
+    becomes label k (coordinates gathered, triangles renamed, neighbour lists
+    rebuilt ascending in the new labels)."""
+    from oracle import mesh as omesh
+    from oracle import orderings as oord
+    old2new = oord.inverse(new2old)
+    tri = old2new[np.asarray(m.tri, dtype=np.int64)]
+    return omesh.topology(m.n, tri), np.ascontiguousarray(m.x[new2old]), np.ascontiguousarray(m.y[new2old])
+
+
+def cpu_baseline(m, sweeps, budget_s=3.0, one_core_s=2.0, orderings=("rdr", "ori", "bfs", "random"),
+                 headline="rdr"):
+    """The oracle's float64 Jacobi sweep (plain C, OpenMP static schedule over
+    evenly divided vertices, as in the paper's Section 5.1) on the host, under
+    each ordering the oracle computes itself: all the threads of the process's
+    share, and one thread.  `value` is the headline ordering's rate."""
+    from oracle import mesh as omesh
+    from oracle import orderings as oord
+    from oracle import quality as oq
+    from oracle import smooth as osm
+    cores, visible, logical = host_cores()
+    top0 = omesh.topology(m.n, m.tri)
+    free = int((top0.fixed == 0).sum())
+    per = {}
+    for kind in orderings:
+        t0 = time.perf_counter()
+        if kind == "ori":
+            p = oord.ori(top0)
+        elif kind == "bfs":
+            p = oord.bfs(top0)
+        elif kind == "rdr":
+            p = oord.rdr(top0, oq.vertex_quality(m.x, m.y, m.tri, m.n))
+        else:
+            p = oord.random_order(m.n, RANDOM_SEED)
+        t_order = time.perf_counter() - t0
+        top, x, y = relabelled(m, top0, p)
+        row = {"oracle_order_seconds": t_order}
+        for label, threads, budget in (("all", cores, budget_s), ("one_core", 1, one_core_s)):
+            # runs of k sweeps (fewer than the workload's when one run would
+            # overshoot the budget) repeated for about `budget` seconds
+            k = max(1, min(sweeps, int(budget * 2e7 * threads / max(1, free))))
+            reps = 0
+            w0 = time.perf_counter()
+            while reps < 1 or time.perf_counter() - w0 < budget:
+                osm.jacobi(top, x, y, k, threads=threads)
+                reps += 1
+            wall = time.perf_counter() - w0
+            row[label] = dict(value=free * k * reps / wall, threads=threads,
+                              sample=f"{k} sweeps x {reps} runs in {wall:.2f} s")
+        per[kind] = row
+        log(f"oracle {kind:7s}: {row['all']['value'] / 1e9:.3f} G upd/s on {cores} threads, "
+            f"{row['one_core']['value'] / 1e9:.3f} G on one")
+    h = per[headline]
+    out = dict(value=h["all"]["value"], unit="vertex-updates/s", cores=cores, kind="oracle",
+               sample=f"{sweeps}-sweep float64 Jacobi runs of the full workload ({m.n} vertices) in "
+                      f"{headline.upper()} labels, {h['all']['sample']}, OpenMP static schedule over "
+                      f"{cores} threads (the process's host share; {visible} CPUs in its affinity mask, "
+                      f"{logical} on the host)",
+               host_cpu=host_cpu_model(), affinity_cpus=visible, host_logical_cpus=logical,
+               one_core_value=h["one_core"]["value"], per_ordering=per)
+    # the paper's gain metric (T_algo - T_RDR) / T_algo on the CPU (Figure 13)
+    if "rdr" in per:
+        for label in ("all", "one_core"):
+            out[f"rdr_gain_{label}"] = {a: 1.0 - per[a][label]["value"] / per["rdr"][label]["value"]
+                                        for a in per if a != "rdr"}
+    return out, top0
 
 
 def host_cpu_model():
+    model = None
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                    model = line.split(":", 1)[1].strip()
+                    break
     except OSError:
         pass
-    return None
+    try:
+        import subprocess
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        info = dict(l.split(":", 1) for l in r.stdout.splitlines() if ":" in l)
+        info = {k.strip(): v.strip() for k, v in info.items()}
+        parts = [info.get("Model name") or model or "unknown CPU"]
+        for key in ("Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+            if key in info:
+                parts.append(f"{key} {info[key]}")
+        return ", ".join(parts)
+    except Exception:
+        return model
 
 
 def result_line(value, steps, warmup, ms_per_step, dtype, config, roofline, cpu, **extra):
@@ -291,6 +354,11 @@ def roofline_of(r, prec="f64", workload="ocean"):
            "bytes_per_launch": k * r["bytes_per_sweep"], "avg_launch_us": launch_us,
            "avg_launch_us_whole_call": k * r["sweep_us_events"],
            "launch_duration": "marginal" if r.get("launch_us_marginal") else "whole call"}
+    # against the bytes one pass must move at least, whatever its depth: every
+    # coordinate read once, every free one written once, the index read once
+    # (one B_sweep per launch); this fraction cannot exceed 1 on HBM-resident data
+    out["pass_floor_bytes"] = r["bytes_per_sweep"]
+    out["frac_pass_floor"] = r["bytes_per_sweep"] / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS
     if traffic is not None and launch_us > 0:
         # the bytes the launch really moves (counters) over its measured duration
         out["traffic_gbs"] = traffic / (launch_us * 1e-6) / 1e9
@@ -373,6 +441,7 @@ def bench_ocean(torch, args):
         # locality of each ordering (host): reuse-distance quantiles of one
         # sweep's access trace (Table 2's measure) and cache lines per wavefront
         extras["reuse_profile"] = {}
+        extras["reuse_profile_algorithm1"] = {}
         for kind in ORDER_NAMES:
             M.reorder(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)
             p = M.reuse_profile((0.5, 0.75, 0.9, 1.0))
@@ -380,6 +449,11 @@ def bench_ocean(torch, args):
                                                  accesses=p["accesses"], lines_per_wave=p["lines_per_wave"])
             log(f"reuse distance {kind:7s}: quantiles 50/75/90/100% {p['quantiles']}  "
                 f"lines per wavefront {p['lines_per_wave']:.1f}")
+            # the trace of Algorithm 1's loop body: the sweep plus the quality upkeep
+            p = M.reuse_profile((0.5, 0.75, 0.9, 1.0), trace="algorithm1")
+            extras["reuse_profile_algorithm1"][kind] = dict(quantiles_50_75_90_100=p["quantiles"], mean=p["mean"],
+                                                            accesses_per_vertex=p["accesses"] / info["n"])
+            log(f"reuse distance {kind:7s} (Algorithm 1 trace): quantiles 50/75/90/100% {p['quantiles']}")
         extras["stream_copy_gbs"] = stream_copy_gbs(torch)
         extras["host_seconds"] = dict(generate=t_gen, build_csr=t_csr,
                                       **{f"reorder_{k}": v for k, v in reorder_s.items()})
@@ -405,6 +479,10 @@ def bench_ocean(torch, args):
             "speedup_rdr_32_cores_vs_ori_1_core": 75, "gain_rdr_vs_bfs": 0.32, "gain_rdr_vs_ori": 0.30,
             "precision": "float64", "workload": "nine Triangle meshes, 299k-393k vertices (Table 1), to dQ < 5e-6"}
         del x, y, x0, y0
+    if not args.no_extras and not args.no_large:
+        del M
+        torch.cuda.empty_cache()
+        extras.update(large_configs(torch, args))
     cpu = None
     if not args.no_cpu_baseline:
         cpu, _ = cpu_baseline(m, SWEEPS)
@@ -421,6 +499,91 @@ def bench_ocean(torch, args):
 
 def strip(results):
     return {k: {kk: vv for kk, vv in v.items() if kk not in ("wall", "ev_ms")} for k, v in results.items()}
+
+
+def config_rows(torch, M, m, workload, kinds, sweeps, steps, warmup):
+    """Fixed-K runs of `sweeps` sweeps under each ordering and precision, each
+    with the roofline block of its sweep kernel."""
+    rows, reorder_s = {}, {}
+    for kind in kinds:
+        t0 = time.perf_counter()
+        M.reorder(kind, seed=RANDOM_SEED, x0=m.x, y0=m.y)
+        reorder_s[kind] = time.perf_counter() - t0
+        for prec in ("f64", "f32"):
+            r, _ = run_fixed(torch, M, m, kind, prec, sweeps, steps, warmup)
+            roof = roofline_of(r, prec, workload)
+            rows[f"{kind}_{prec}"] = dict(vertex_updates_per_s=r["vertex_updates_per_s"],
+                                          ms_per_step=r["ms_per_step"], sweep_kernel=r["sweep_kernel"],
+                                          roofline=roof)
+            log(f"{workload} {kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  frac "
+                f"{roof['frac']:.3f}  pass floor {roof['frac_pass_floor']:.3f}  "
+                f"physical {roof.get('traffic_frac', float('nan')):.3f}  [{r['sweep_kernel']}]")
+    return rows, reorder_s
+
+
+def to_criterion(torch, M, m, workload):
+    """Algorithm 1 to the paper's criterion (Section 5.1: dQ < 5e-6), quality
+    fused into the sweep passes, float64 and float32 coordinates, under the
+    handle's ordering: sweeps, the stop, and the wall time of the call."""
+    out = {}
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        x0 = torch.as_tensor(m.x, dtype=dt, device="cuda")
+        y0 = torch.as_tensor(m.y, dtype=dt, device="cuda")
+        x, y = torch.empty_like(x0), torch.empty_like(y0)
+        M.permute(x0, y0, x, y)
+        M.smooth(x, y, max_iters=2000, tol=5e-6)              # tunes, builds plans, captures graphs
+        M.permute(x0, y0, x, y)
+        with Timer(torch) as t:
+            r = M.smooth(x, y, max_iters=2000, tol=5e-6)
+        out[prec] = dict(iters=r["iters"], stopped_by=r["stopped_by"], q0=r["q0"], q_final=r["q_final"],
+                         seconds=t.wall, stop_variant=(re.search(r"stop=(\S+)", M.sweep_config(prec)) or [None, None])[1])
+        log(f"{workload} to the criterion ({prec}): {r['iters']} sweeps in {t.wall * 1e3:.2f} ms")
+        del x0, y0, x, y
+    return out
+
+
+def large_configs(torch, args):
+    """The two HBM-resident configurations, in the default run: the graded
+    16M-vertex mesh (100 sweeps) and the 512-mesh batch (30 sweeps), under RDR
+    and ORI in float64 and float32, each with its roofline blocks and the
+    float32 position error against the float64 form on the same GPU."""
+    import meshgen
+    from paper_1606_00803_amd import lms
+    out = {}
+    t0 = time.perf_counter()
+    m = meshgen.graded16m()
+    t_gen = time.perf_counter() - t0
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    info = M.info()
+    log(f"graded mesh n={info['n']} n_free={info['n_free']} T={m.T} nnz={info['nnz']} gen={t_gen:.1f}s")
+    rows, reorder_s = config_rows(torch, M, m, "graded16m", ("rdr", "ori"), 100, args.large_steps, 1)
+    M.reorder("rdr", x0=m.x, y0=m.y)
+    err = fp32_vs_fp64(torch, M, m, 100)
+    log(f"graded16m float32 against float64 after 100 sweeps: max {err['max']:.3e}, rms {err['rms']:.3e}")
+    crit = to_criterion(torch, M, m, "graded16m")
+    out["graded16m"] = dict(workload="graded mesh refined 4x toward a seeded curve, 100 Jacobi sweeps per step",
+                            n=info["n"], n_free=info["n_free"], n_tri=m.T, nnz=info["nnz"], sweeps_per_step=100,
+                            steps=args.large_steps, per_ordering=rows, fp32_vs_fp64_rdr=err, to_criterion_rdr=crit,
+                            host_seconds=dict(generate=t_gen, **{f"reorder_{k}": v for k, v in reorder_s.items()}))
+    del M, m
+    t0 = time.perf_counter()
+    ms = meshgen.batch()
+    u, v_off, t_off = meshgen.concat(ms)
+    B = lms.Mesh.build_csr_batched(v_off, t_off, np.concatenate([mm.tri for mm in ms]))
+    t_gen = time.perf_counter() - t0
+    info = B.info()
+    log(f"batch: {len(ms)} meshes, n={info['n']} T={u.T} nnz={info['nnz']} ({t_gen:.1f}s)")
+    rows, reorder_s = config_rows(torch, B, u, "batch512", ("rdr", "ori"), 30, args.large_steps, 1)
+    B.reorder("rdr", x0=u.x, y0=u.y)
+    err = fp32_vs_fp64(torch, B, u, 30)
+    log(f"batch512 float32 against float64 after 30 sweeps: max {err['max']:.3e}, rms {err['rms']:.3e}")
+    out["batch512"] = dict(workload=f"batch of {len(ms)} jittered grids, sizes log-uniform 1k-200k vertices, "
+                                    "30 sweeps per step, one launch per pass over all meshes",
+                           n=info["n"], n_free=info["n_free"], n_mesh=len(ms), nnz=info["nnz"], sweeps_per_step=30,
+                           steps=args.large_steps, per_ordering=rows, fp32_vs_fp64_rdr=err,
+                           host_seconds=dict(generate_and_build=t_gen,
+                                             **{f"reorder_{k}": v for k, v in reorder_s.items()}))
+    return out
 
 
 def bench_graded16m(torch, args):
@@ -470,7 +633,7 @@ def bench_graded16m(torch, args):
         extras[f"quality_pass_rdr_{prec}"] = q
     cpu = None
     if not args.no_cpu_baseline and "f32" in finals:
-        cpu, top = cpu_baseline(m, SWEEPS, budget_s=0.0)
+        cpu, top = cpu_baseline(m, SWEEPS, budget_s=1.0, one_core_s=0.5, orderings=("ori",), headline="ori")
         from oracle import smooth as osm
         ex, ey = osm.jacobi(top, m.x, m.y, SWEEPS, threads=cpu["cores"])
         ext = float(np.ptp(m.xy, axis=0).max())
@@ -639,6 +802,9 @@ def main():
     ap.add_argument("--orderings", default=",".join(ORDER_NAMES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the per-ordering timings")
+    ap.add_argument("--no-large", action="store_true",
+                    help="leave the graded 16M-vertex mesh and the 512-mesh batch out of the default run")
+    ap.add_argument("--large-steps", type=int, default=5, help="timed steps of each large configuration")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a known-size kernel for counters)")
     args = ap.parse_args()

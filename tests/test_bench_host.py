@@ -90,10 +90,41 @@ def test_counter_summary_is_used_only_for_the_current_source(tmp_path):
 
 def test_oracle_baseline_reports_its_sample():
     m = meshgen.jittered_grid(40, seed=1)
-    cpu, top = bench.cpu_baseline(m, 3, budget_s=0.0, one_core_s=0.05)
+    cpu, top = bench.cpu_baseline(m, 3, budget_s=0.0, one_core_s=0.0)
     free = int((top.fixed == 0).sum())
     assert cpu["kind"] == "oracle" and cpu["unit"] == "vertex-updates/s"
     assert 1 <= cpu["cores"] <= 16 and cpu["value"] > 0 and cpu["one_core_value"] > 0
+    assert cpu["cores"] <= cpu["affinity_cpus"] <= cpu["host_logical_cpus"]
     assert f"{m.n} vertices" in cpu["sample"] and free > 0
-    assert "one thread" in cpu["one_core_sample"]
+    # every ordering is timed, on all threads and on one, with the paper's gain metric
+    assert set(cpu["per_ordering"]) == {"rdr", "ori", "bfs", "random"}
+    for row in cpu["per_ordering"].values():
+        assert row["all"]["value"] > 0 and row["one_core"]["threads"] == 1
+    assert set(cpu["rdr_gain_all"]) == {"ori", "bfs", "random"}
+    assert cpu["value"] == cpu["per_ordering"]["rdr"]["all"]["value"]
     assert np.isfinite(cpu["value"])
+
+
+def test_relabelled_mesh_sweeps_to_the_same_positions():
+    # the oracle's view of an ordering: after the inverse permutation, a sweep
+    # gives the input-label result (sums reordered, so within rounding)
+    from oracle import mesh as omesh
+    from oracle import orderings as oord
+    from oracle import smooth as osm
+    m = meshgen.jittered_grid(30, seed=2, land_fraction=0.3)
+    top0 = omesh.topology(m.n, m.tri)
+    ex, ey = osm.jacobi(top0, m.x, m.y, 4)
+    p = oord.random_order(m.n, 5)
+    top, x, y = bench.relabelled(m, top0, p)
+    gx, gy = osm.jacobi(top, x, y, 4)
+    inv = oord.inverse(p)
+    assert np.max(np.abs(gx[inv] - ex)) <= 1e-14 and np.max(np.abs(gy[inv] - ey)) <= 1e-14
+
+
+def test_pass_floor_fraction_charges_one_sweep_per_launch():
+    r = dict(sweep_kernel="tb/ts1024/k4/bs1024/w8/r2/l2048/xcd16/patch", bytes_per_sweep=8_000_000,
+             sweep_us_events=1.0, launch_us_marginal=4.0)
+    roof = bench.roofline_of(r, "f64", "no-such-workload")
+    assert roof["frac"] == pytest.approx(4 * 8e6 / 4e-6 / 1e9 / 8000)
+    assert roof["frac_pass_floor"] == pytest.approx(8e6 / 4e-6 / 1e9 / 8000)
+    assert roof["pass_floor_bytes"] == 8_000_000
