@@ -561,6 +561,16 @@ def large_configs(torch, args):
     err = fp32_vs_fp64(torch, M, m, 100)
     log(f"graded16m float32 against float64 after 100 sweeps: max {err['max']:.3e}, rms {err['rms']:.3e}")
     crit = to_criterion(torch, M, m, "graded16m")
+    # the breadth-first ordering on the host and on the device (same order)
+    t0 = time.perf_counter()
+    want = M.reorder("bfs")
+    reorder_s["bfs"] = time.perf_counter() - t0
+    M.reorder_device("bfs")                  # uploads the input arrays once
+    t0 = time.perf_counter()
+    got = M.reorder_device("bfs")
+    reorder_s["bfs_device"] = time.perf_counter() - t0
+    assert np.array_equal(want, got)
+    log(f"graded16m reorder bfs: host {reorder_s['bfs']:.3f} s, device {reorder_s['bfs_device']:.3f} s")
     out["graded16m"] = dict(workload="graded mesh refined 4x toward a seeded curve, 100 Jacobi sweeps per step",
                             n=info["n"], n_free=info["n_free"], n_tri=m.T, nnz=info["nnz"], sweeps_per_step=100,
                             steps=args.large_steps, per_ordering=rows, fp32_vs_fp64_rdr=err, to_criterion_rdr=crit,

@@ -176,11 +176,22 @@ __global__ void k_cc_shortcut(int32_t *comp, int32_t n, int32_t *changed) {
 }
 
 // ---- breadth-first search ------------------------------------------------
+// root flags and component sizes; a wavefront whose vertices all lie in one
+// component (the usual case) adds its count with one atomic instead of 64
 __global__ void k_root_flags(const int32_t *__restrict__ comp, int64_t *flag, int64_t *size_at_root, int32_t n) {
     const int32_t v = int32_t(blockIdx.x) * kBS + int32_t(threadIdx.x);
-    if (v >= n) return;
-    flag[v] = comp[v] == v ? 1 : 0;
-    atomicAdd(reinterpret_cast<unsigned long long *>(&size_at_root[comp[v]]), 1ull);
+    const bool valid = v < n;
+    const int32_t c = valid ? comp[v] : -1;
+    if (valid) flag[v] = c == v ? 1 : 0;
+    const int32_t c0 = __shfl(c, 0, 64);
+    const bool uniform = __all(!valid || c == c0);
+    if (uniform) {
+        const int cnt = __popcll(__ballot(valid));
+        if ((threadIdx.x & 63) == 0 && c0 >= 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&size_at_root[c0]), (unsigned long long)cnt);
+    } else if (valid) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&size_at_root[c]), 1ull);
+    }
 }
 
 // frontier 0: the roots in ascending label; claim[root] = (0 << 32) | position
@@ -195,82 +206,182 @@ __global__ void k_seed(const int32_t *__restrict__ comp, const int64_t *__restri
     }
 }
 
-__global__ void k_bfs_claim(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                            const int32_t *__restrict__ front, int64_t m, uint64_t tag, uint64_t *claim) {
-    const int64_t i = int64_t(blockIdx.x) * kBS + threadIdx.x;
-    if (i >= m) return;
-    const int32_t v = front[i];
-    const uint64_t want = tag | uint64_t(i);
-    for (int64_t j = ptr[v]; j < ptr[v + 1]; ++j)
-        atomicMin(reinterpret_cast<unsigned long long *>(&claim[adj[j]]), (unsigned long long)want);
-}
+// ---- the whole level loop in one workgroup --------------------------------
+// Frontiers of these meshes hold hundreds to tens of thousands of vertices
+// over thousands of levels, so one workgroup runs every level, with workgroup
+// barriers between the phases instead of a launch (and a host round trip for
+// the next frontier's size) per level.  A frontier of up to kFrontLds
+// vertices, the next frontier of a frontier of at most one chunk, stays in
+// LDS; any other goes to global memory.  Per level, in
+// frontier order:
+//   1. place each entry after its component's earlier levels, at its offset
+//      from the first entry of its component in this level (the frontier
+//      keeps components in rank order, each contiguous), and claim every
+//      neighbour for the earliest position that reaches it (atomicMin on
+//      (level, position));
+//   2. the last entry of each component adds the level's count to it, each
+//      entry counts the neighbours it claimed, an exclusive scan gives its
+//      offset in the next frontier, and it appends them in ascending label.
+// Claims and component counts are read and written with device-scope
+// atomics; a frontier in global memory is read after a device-scope fence on
+// each side of the barrier.
 
-__global__ void k_bfs_count(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                            const int32_t *__restrict__ front, int64_t m, uint64_t tag,
-                            const uint64_t *__restrict__ claim, int64_t *cnt) {
-    const int64_t i = int64_t(blockIdx.x) * kBS + threadIdx.x;
-    if (i >= m) return;
-    const int32_t v = front[i];
-    const uint64_t want = tag | uint64_t(i);
-    int64_t c = 0;
-    for (int64_t j = ptr[v]; j < ptr[v + 1]; ++j) c += claim[adj[j]] == want ? 1 : 0;
-    cnt[i] = c;
-}
+constexpr int kOneBS = 1024;
+constexpr int kFrontLds = 7936;  // two LDS frontiers within 64 KiB
 
-__global__ void k_bfs_emit(const int64_t *__restrict__ ptr, const int32_t *__restrict__ adj,
-                           const int32_t *__restrict__ front, int64_t m, uint64_t tag,
-                           const uint64_t *__restrict__ claim, const int64_t *__restrict__ off, int32_t *next) {
-    const int64_t i = int64_t(blockIdx.x) * kBS + threadIdx.x;
-    if (i >= m) return;
-    const int32_t v = front[i];
-    const uint64_t want = tag | uint64_t(i);
-    int64_t o = off[i];
-    for (int64_t j = ptr[v]; j < ptr[v + 1]; ++j)
-        if (claim[adj[j]] == want) next[o++] = adj[j];
-}
+enum class ScanOp { Sum, Max };
 
-// placement of one level: the level's entries of component c are contiguous
-// (the frontier keeps components in rank order); they go after the
-// component's earlier levels
-__global__ void k_level_first(const int32_t *__restrict__ front, int64_t m, const int32_t *__restrict__ comp,
-                              int64_t *first, int64_t *count) {
-    const int64_t p = int64_t(blockIdx.x) * kBS + threadIdx.x;
-    if (p >= m) return;
-    const int32_t c = comp[front[p]];
-    atomicMin(reinterpret_cast<unsigned long long *>(&first[c]), (unsigned long long)p);
-    atomicAdd(reinterpret_cast<unsigned long long *>(&count[c]), 1ull);
-}
-
-__global__ void k_level_place(const int32_t *__restrict__ front, int64_t m, const int32_t *__restrict__ comp,
-                              const int64_t *__restrict__ first, const int64_t *__restrict__ comp_start,
-                              const int64_t *__restrict__ done, int32_t *order, int32_t n, int32_t *bad) {
-    const int64_t p = int64_t(blockIdx.x) * kBS + threadIdx.x;
-    if (p >= m) return;
-    const int32_t v = front[p];
-    const int32_t c = comp[v];
-    const int64_t at = comp_start[c] + done[c] + (p - first[c]);
-    if (at < comp_start[c] || at >= comp_start[c + 1] || at >= n) {  // never, when components stay contiguous
-        *bad = 1;
-        return;
+// Inclusive scan of v over the workgroup (wave shuffles, then the wave
+// totals in LDS); *total receives the reduction of the whole workgroup.
+template <ScanOp OP>
+__device__ int64_t wg_scan_incl(int64_t v, int64_t *s_w, int64_t *total) {
+    const int lane = int(threadIdx.x) & 63, w = int(threadIdx.x) >> 6;
+    auto op = [](int64_t a, int64_t b) { return OP == ScanOp::Sum ? a + b : (a > b ? a : b); };
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t t = __shfl_up(v, off, 64);
+        if (lane >= off) v = op(v, t);
     }
-    order[at] = v;
-}
-
-__global__ void k_level_done(const int32_t *__restrict__ front, int64_t m, const int32_t *__restrict__ comp,
-                             int64_t *first, int64_t *count, int64_t *done) {
-    const int64_t p = int64_t(blockIdx.x) * kBS + threadIdx.x;
-    if (p >= m) return;
-    const int32_t c = comp[front[p]];
-    if (first[c] == p) {  // one thread per component present in this level
-        done[c] += count[c];
-        first[c] = int64_t(~uint64_t(0) >> 1);
-        count[c] = 0;
+    if (lane == 63) s_w[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = OP == ScanOp::Sum ? 0 : -1;
+        for (int i = 0; i < kOneBS / 64; ++i) {
+            const int64_t t = s_w[i];
+            s_w[i] = run;  // what the waves before wave i hold
+            run = op(run, t);
+        }
+        s_w[kOneBS / 64] = run;
     }
+    __syncthreads();
+    const int64_t r = op(s_w[w], v);
+    *total = s_w[kOneBS / 64];
+    __syncthreads();  // s_w is reused by the next scan
+    return r;
 }
 
-__global__ void k_fill_i64(int64_t *a, int64_t n, int64_t v) {
-    const int64_t i = int64_t(blockIdx.x) * kBS + threadIdx.x;
-    if (i < n) a[i] = v;
+__device__ __forceinline__ int64_t load_done(int64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_claim(uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kOneBS) void k_bfs_one_group(const int64_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ adj,
+                                                         const int32_t *__restrict__ comp,
+                                                         const int64_t *__restrict__ comp_start, int64_t *done,
+                                                         uint64_t *claim, int32_t *ga, int32_t *gb, int64_t m0,
+                                                         int32_t *order, int32_t n, int32_t *bad,
+                                                         int64_t *placed_out) {
+    __shared__ int64_t s_w[kOneBS / 64 + 1];
+    __shared__ int32_t s_front[2][kFrontLds];
+    const int tid = int(threadIdx.x);
+    // the first frontier (the roots) arrives in ga
+    int32_t *front = ga;
+    int64_t m = m0, placed = 0;
+    for (uint64_t level = 0; m > 0; ++level) {
+        if (level > uint64_t(n)) {  // cannot happen: every level places at least one vertex
+            if (tid == 0) *bad = 1;
+            break;
+        }
+        const uint64_t tag = (level + 1) << 32;
+        // 1. placement and claims
+        int64_t carry = -1;  // first position of the component running into this chunk
+        for (int64_t base = 0; base < m; base += kOneBS) {
+            const int64_t p = base + tid;
+            const bool valid = p < m;
+            const int32_t v = valid ? front[p] : 0;
+            const int32_t c = valid ? comp[v] : -1;
+            const bool head = valid && (p == 0 || comp[front[p - 1]] != c);
+            int64_t chunk_max;
+            int64_t first = wg_scan_incl<ScanOp::Max>(head ? p : -1, s_w, &chunk_max);
+            if (first < 0) first = carry;
+            carry = chunk_max >= 0 ? chunk_max : carry;
+            if (valid) {
+                const int64_t at = comp_start[c] + load_done(&done[c]) + (p - first);
+                if (first < 0 || at < comp_start[c] || at >= comp_start[c + 1] || at >= n)
+                    *bad = 1;
+                else
+                    order[at] = v;
+                const uint64_t want = tag | uint64_t(p);
+                for (int64_t j = ptr[v]; j < ptr[v + 1]; ++j)
+                    atomicMin(reinterpret_cast<unsigned long long *>(&claim[adj[j]]), (unsigned long long)want);
+            }
+        }
+        __threadfence();  // the claims are complete before any is counted
+        __syncthreads();
+        // 2. claimed neighbours and the next frontier: its size is known
+        // before any entry is written when the frontier is one chunk, and the
+        // next frontier stays in LDS if it fits; otherwise it goes to the
+        // global buffer the current frontier does not use
+        int32_t *lds_next = front == s_front[0] ? s_front[1] : s_front[0];
+        int32_t *glb_next = front == ga ? gb : ga;
+        int32_t *nf = glb_next;
+        int64_t cap = n;
+        int64_t total = 0;  // the next frontier's size
+        for (int64_t base = 0; base < m; base += kOneBS) {
+            const int64_t p = base + tid;
+            const bool valid = p < m;
+            int64_t cnt = 0;
+            int32_t v = 0;
+            int64_t j0 = 0, j1 = 0;
+            uint32_t mine = 0;  // which of the first 32 neighbours this entry claimed
+            const uint64_t want = tag | uint64_t(p);
+            if (valid) {
+                v = front[p];
+                j0 = ptr[v];
+                j1 = ptr[v + 1];
+                for (int64_t j = j0; j < j1; ++j)
+                    if (load_claim(&claim[adj[j]]) == want) {
+                        ++cnt;
+                        if (j - j0 < 32) mine |= 1u << (j - j0);
+                    }
+            }
+            int64_t chunk_total;
+            const int64_t o0 = total + wg_scan_incl<ScanOp::Sum>(cnt, s_w, &chunk_total) - cnt;
+            total += chunk_total;
+            if (m <= kOneBS && total <= kFrontLds) {  // the same for every thread
+                nf = lds_next;
+                cap = kFrontLds;
+            }
+            if (valid) {
+                int64_t o = o0;
+                for (int64_t j = j0; j < j1; ++j) {
+                    const int32_t u = adj[j];
+                    if (j - j0 < 32 ? ((mine >> (j - j0)) & 1u) != 0 : load_claim(&claim[u]) == want) {
+                        if (o < cap)
+                            nf[o] = u;
+                        else
+                            *bad = 1;
+                        ++o;
+                    }
+                }
+            }
+        }
+        // the component counts, once every placement of the level has read them
+        __syncthreads();
+        int64_t carry2 = -1;
+        for (int64_t base = 0; base < m; base += kOneBS) {
+            const int64_t p = base + tid;
+            const bool valid = p < m;
+            const int32_t c = valid ? comp[front[p]] : -1;
+            const bool head = valid && (p == 0 || comp[front[p - 1]] != c);
+            int64_t chunk_max;
+            int64_t first = wg_scan_incl<ScanOp::Max>(head ? p : -1, s_w, &chunk_max);
+            if (first < 0) first = carry2;
+            carry2 = chunk_max >= 0 ? chunk_max : carry2;
+            if (valid && (p + 1 == m || comp[front[p + 1]] != c))
+                __hip_atomic_fetch_add(&done[c], p - first + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();  // a frontier in global memory, and the counts, are complete
+        __syncthreads();
+        if (nf == glb_next) __threadfence();  // and no stale copy of it stays in this CU's cache
+        placed += m;
+        front = nf;
+        m = total <= cap ? total : 0;
+    }
+    if (tid == 0) *placed_out = placed;
 }
 
 // ---- relabelling -----------------------------------------------------------
@@ -515,38 +626,18 @@ void bfs_device(Mesh &M, ReorderState &R, hipStream_t s, DBuf<int32_t> &order) {
     RHIP_CHECK(hipStreamSynchronize(s));
     DBuf<int32_t> fa(static_cast<size_t>(n)), fb(static_cast<size_t>(n));
     DBuf<uint64_t> claim(static_cast<size_t>(n));
-    DBuf<int64_t> cnt(static_cast<size_t>(n)), off(static_cast<size_t>(n) + 1), first(static_cast<size_t>(n)), count(static_cast<size_t>(n)), done(static_cast<size_t>(n));
+    DBuf<int64_t> done(static_cast<size_t>(n)), placed_d(1);
     k_seed<<<blocks_for(n), kBS, 0, s>>>(comp.p, rank.p, fa.p, claim.p, n);
-    k_fill_i64<<<blocks_for(n), kBS, 0, s>>>(first.p, n, int64_t(~uint64_t(0) >> 1));
     rlaunch_check();
-    RHIP_CHECK(hipMemsetAsync(count.p, 0, sizeof(int64_t) * size_t(n), s));
     RHIP_CHECK(hipMemsetAsync(done.p, 0, sizeof(int64_t) * size_t(n), s));
     RHIP_CHECK(hipMemsetAsync(changed.p, 0, sizeof(int32_t), s));  // reused as the placement check
-    int32_t *front = fa.p, *next = fb.p;
-    int64_t m = roots, placed = 0;
-    for (uint64_t level = 0; m > 0; ++level) {
-        if (level >= uint64_t(n) + 1) fail(LMS_ERR_STATE, "breadth-first search did not end");
-        k_level_first<<<blocks_for(m), kBS, 0, s>>>(front, m, comp.p, first.p, count.p);
-        k_level_place<<<blocks_for(m), kBS, 0, s>>>(front, m, comp.p, first.p, comp_start.p, done.p, order.p, n,
-                                                    changed.p);
-        k_level_done<<<blocks_for(m), kBS, 0, s>>>(front, m, comp.p, first.p, count.p, done.p);
-        const uint64_t tag = (level + 1) << 32;
-        k_bfs_claim<<<blocks_for(m), kBS, 0, s>>>(R.ptr0.p, R.adj0.p, front, m, tag, claim.p);
-        k_bfs_count<<<blocks_for(m), kBS, 0, s>>>(R.ptr0.p, R.adj0.p, front, m, tag, claim.p, cnt.p);
-        rlaunch_check();
-        placed += m;
-        scan(cnt.p, off.p, m, s);
-        int64_t mn = 0;
-        RHIP_CHECK(hipMemcpyAsync(&mn, off.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        RHIP_CHECK(hipStreamSynchronize(s));
-        if (mn > 0) {
-            k_bfs_emit<<<blocks_for(m), kBS, 0, s>>>(R.ptr0.p, R.adj0.p, front, m, tag, claim.p, off.p, next);
-            rlaunch_check();
-        }
-        std::swap(front, next);
-        m = mn;
-    }
+    RHIP_CHECK(hipMemsetAsync(placed_d.p, 0, sizeof(int64_t), s));
+    k_bfs_one_group<<<1, kOneBS, 0, s>>>(R.ptr0.p, R.adj0.p, comp.p, comp_start.p, done.p, claim.p, fa.p, fb.p,
+                                         roots, order.p, n, changed.p, placed_d.p);
+    rlaunch_check();
+    int64_t placed = 0;
     int32_t hbad = 0;
+    RHIP_CHECK(hipMemcpyAsync(&placed, placed_d.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RHIP_CHECK(hipMemcpyAsync(&hbad, changed.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     RHIP_CHECK(hipStreamSynchronize(s));
     if (placed != n || hbad) fail(LMS_ERR_STATE, "breadth-first search misplaced vertices");

@@ -745,6 +745,20 @@ def test_device_bfs_matches_the_oracle_on_several_components():
     assert np.array_equal(M.reorder_device("bfs"), oord.bfs(oracle_topology(m)))
 
 
+def test_device_bfs_frontier_paths():
+    # the one-workgroup search keeps a small frontier in LDS and a large one in
+    # global memory: a wheel whose one-vertex first level reaches 9000 rim
+    # vertices (more than fit in LDS), 3000 tiny meshes (3000 roots in the first
+    # frontier, several chunks), and a long strip (thousands of small levels)
+    from paper_1606_00803_amd import lms
+    cases = [meshgen.wheel(9000, seed=8),
+             meshgen.concat(meshgen.batch(count=3000, seed=61, n_min=9, n_max=40))[0],
+             meshgen.jittered_grid(3000, 3, seed=62)]
+    for m in cases:
+        M = lms.Mesh.build_csr(m.n, m.tri)
+        assert np.array_equal(M.reorder_device("bfs"), oord.bfs(oracle_topology(m))), m.n
+
+
 def test_batched_stopping_rule_matches_the_oracle_on_the_union():
     # a batched handle's stopping rule uses Q over all its vertices: the
     # union mesh's Q (fused and separate quality paths alike)
