@@ -424,15 +424,16 @@ def bench_ocean(torch, args):
         x0 = torch.as_tensor(m.x, dtype=torch.float64, device="cuda")
         y0 = torch.as_tensor(m.y, dtype=torch.float64, device="cuda")
         # to the paper's criterion: quality fused into the sweep passes (the
-        # default), and sweep + separate quality pass
-        for label, flag in (("", "1"), ("_separate_quality", "0")):
+        # default), sweep + separate quality pass, and the multicolour scheme
+        for label, flag, scheme in (("", "1", "jacobi"), ("_separate_quality", "0", "jacobi"),
+                                    ("_multicolour", "1", "multicolor")):
             os.environ["LMS_FUSED_QUALITY"] = flag
             try:
                 M.permute(x0, y0, x, y)
-                M.smooth(x, y, max_iters=2000, tol=5e-6)          # tunes and captures the graphs
+                M.smooth(x, y, max_iters=2000, tol=5e-6, scheme=scheme)   # tunes and captures the graphs
                 M.permute(x0, y0, x, y)
                 with Timer(torch) as t:
-                    rr = M.smooth(x, y, max_iters=2000, tol=5e-6)
+                    rr = M.smooth(x, y, max_iters=2000, tol=5e-6, scheme=scheme)
             finally:
                 os.environ.pop("LMS_FUSED_QUALITY", None)
             extras["to_criterion_rdr_f64" + label] = dict(iters=rr["iters"], stopped_by=rr["stopped_by"],
@@ -617,7 +618,7 @@ def bench_graded16m(torch, args):
             results[f"{kind}_{prec}"] = r
             log(f"{kind:7s} {prec}: {r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s  sweep "
                 f"{r['sweep_us_events']:8.2f} us  {r['achieved_gbs']:8.1f} GB/s  [{r['sweep_kernel']}]")
-            if kind == "rdr":
+            if kind == "rdr" and not args.no_extras:
                 # one clean run of exactly SWEEPS sweeps from P_0 for the error metric
                 dt = torch.float64 if prec == "f64" else torch.float32
                 x0 = torch.as_tensor(m.x, dtype=dt, device="cuda")
@@ -675,6 +676,7 @@ def bench_batch512(torch, args):
     B = lms.Mesh.build_csr_batched(v_off, t_off, local)
     info = B.info()
     log(f"batch: {len(ms)} meshes, n={info['n']} T={u.T} nnz={info['nnz']} ({time.perf_counter() - t0:.1f}s)")
+    calibration_copy(torch, args.calibration_copy_mb)
     results = {}
     for kind in ("ori", "rdr"):
         B.reorder(kind, seed=RANDOM_SEED, x0=u.x, y0=u.y)
@@ -686,6 +688,16 @@ def bench_batch512(torch, args):
     extras = {"fp32_vs_fp64_rdr": fp32_vs_fp64(torch, B, u, SWEEPS)}
     log(f"float32 against float64 after {SWEEPS} sweeps: max {extras['fp32_vs_fp64_rdr']['max']:.3e}, "
         f"rms {extras['fp32_vs_fp64_rdr']['rms']:.3e} of extent")
+    h = results["rdr_f64"]
+    line = result_line(
+        h["vertex_updates_per_s"], args.steps, args.warmup, h["ms_per_step"], "f64",
+        {"workload": f"batch of {len(ms)} jittered grids, sizes log-uniform 1k-200k vertices, "
+                     f"{SWEEPS} sweeps each in one launch per sweep, RDR per mesh, float64",
+         "n": info["n"], "n_mesh": len(ms), "sweeps_per_step": SWEEPS},
+        with_stream_copy(torch, roofline_of(h, "f64", "batch512")), None, per_ordering=strip(results),
+        extras=extras)
+    if args.no_extras:
+        return line
     # the same meshes split by size class, each class a batch of its own: the
     # class that fits in LDS (<= 4096 vertices) runs all sweeps in one launch
     # and may beat the per-sweep byte formula; the others run per sweep
@@ -725,14 +737,7 @@ def bench_batch512(torch, args):
                     f"{r['vertex_updates_per_s'] / 1e9:7.2f} G upd/s")
         finally:
             os.environ.pop("LMS_SMALL_BATCH", None)
-    h = results["rdr_f64"]
-    return result_line(
-        h["vertex_updates_per_s"], args.steps, args.warmup, h["ms_per_step"], "f64",
-        {"workload": f"batch of {len(ms)} jittered grids, sizes log-uniform 1k-200k vertices, "
-                     f"{SWEEPS} sweeps each in one launch per sweep, RDR per mesh, float64",
-         "n": info["n"], "n_mesh": len(ms), "sweeps_per_step": SWEEPS},
-        with_stream_copy(torch, roofline_of(h, "f64", "batch512")), None, per_ordering=strip(results),
-        extras=extras)
+    return line
 
 
 def bench_graded64m(torch, args):
