@@ -138,3 +138,76 @@ def test_batch512_full_size_matches_the_oracle_per_mesh(batch512, prec):
         assert worst <= TOL64
     else:
         assert worst <= 1e-5 and worst_rms <= 1e-6
+
+
+def _crop(m, cx, cy, half):
+    """The triangles with every corner inside the square of half-width `half`
+    around (cx, cy), relabelled compactly: (local mesh, global ids of its
+    vertices)."""
+    inside = (np.abs(m.xy[:, 0] - cx) <= half) & (np.abs(m.xy[:, 1] - cy) <= half)
+    keep = inside[m.tri].all(axis=1)
+    tri = m.tri[keep]
+    ids = np.unique(tri)
+    local = np.full(m.n, -1, dtype=np.int64)
+    local[ids] = np.arange(ids.size)
+    return meshgen.Mesh(m.xy[ids], local[tri].astype(np.int32), {}), ids
+
+
+def test_graded64m_to_the_criterion_sampled_against_the_oracle():
+    # the 64M-vertex configuration (holes, two refinement bands), RDR, float32
+    # coordinates with the float64 quality fused into the passes, run to the
+    # paper's criterion (Section 5.1); P_K at sampled vertices against the
+    # float64 oracle.  P_K(v) depends only on P_0 within graph distance K, so
+    # the oracle sweeps a cropped piece of the mesh around each sample; the
+    # crop is checked to hold every triangle of the vertices within distance
+    # K + 1 of the sample (their triangle counts equal the whole mesh's).
+    import torch
+    from oracle import mesh as omesh
+    from paper_1606_00803_amd import lms
+    m = meshgen.graded64m()
+    print("generated", m.n, flush=True)
+    M = lms.Mesh.build_csr(m.n, m.tri)
+    M.reorder_device("rdr", x0=m.x, y0=m.y)
+    x0 = to_dev(m.x, torch.float32)
+    y0 = to_dev(m.y, torch.float32)
+    x, y = torch.empty_like(x0), torch.empty_like(y0)
+    M.permute(x0, y0, x, y)
+    r = M.smooth(x, y, max_iters=2000, tol=5e-6)
+    print("smoothed", r, M.sweep_config("f32").split(" ")[0], flush=True)
+    assert r["stopped_by"] == "tol" and 20 <= r["iters"] <= 200
+    M.permute(x, y, x0, y0, inverse=True)
+    gx = x0.double().cpu().numpy()
+    gy = y0.double().cpu().numpy()
+    del x, y, x0, y0, M
+    K = r["iters"]
+    e = extent(m.xy)
+    tcount = np.bincount(m.tri.ravel(), minlength=m.n)
+    rng = np.random.default_rng(64)
+    errs = []
+    for cx, cy in m.xy[rng.integers(0, m.n, size=6)]:   # centres on the mesh, not in a hole
+        sub, ids = _crop(m, cx, cy, 0.035)
+        top = omesh.topology(sub.n, sub.tri)
+        free = np.flatnonzero((top.fixed == 0) & (np.hypot(sub.xy[:, 0] - cx, sub.xy[:, 1] - cy) < 0.004))
+        if free.size == 0:          # the centre fell in a hole
+            continue
+        sample = rng.choice(free, min(8, free.size), replace=False)
+        # every vertex within distance K + 1 of a sample keeps all its triangles in the crop
+        dist = {int(v): 0 for v in sample}
+        front = list(dist)
+        for d in range(1, K + 2):
+            nxt = []
+            for w in front:
+                for u in top.neighbours(w).tolist():
+                    if u not in dist:
+                        dist[u] = d
+                        nxt.append(u)
+            front = nxt
+        ball = np.array(sorted(dist))
+        assert np.array_equal(np.bincount(sub.tri.ravel(), minlength=sub.n)[ball], tcount[ids[ball]])
+        ex, ey = osm.jacobi_at_vertices(top, sub.x, sub.y, K, sample)
+        g = ids[sample]
+        errs.append(np.hypot(gx[g] - ex, gy[g] - ey) / e)
+    d = np.concatenate(errs)
+    print("sampled", d.size, "max", d.max(), "rms", math.sqrt(np.mean(d * d)), flush=True)
+    assert d.size >= 16
+    assert d.max() <= 1e-5 and math.sqrt(np.mean(d * d)) <= 1e-6
