@@ -80,6 +80,9 @@ struct DeviceState {
         int32_t *tile_ptr = nullptr, *ring = nullptr, *halo = nullptr;
         int64_t *halo_ptr = nullptr, *lidx_ptr = nullptr;
         uint16_t *lidx = nullptr;
+        // patch plans: the working copies are stored patch by patch, position
+        // p holding label pm_label[p] (halo and qc_ids then hold positions)
+        int32_t *pm_label = nullptr;
         // quality-fused form (uploaded on first use under the stopping rule)
         bool q_ready = false, q_fits = false;
         int64_t *qtri_ptr = nullptr;
@@ -593,6 +596,34 @@ const DeviceState::TBDev *find_tb(const DeviceState &d, const TBShape &t) {
     return nullptr;
 }
 
+// Patch-major order of a patch plan: tile t's own rows (in its list order)
+// at positions tile_ptr[t] .. tile_ptr[t+1]-1, then the rows no tile owns
+// (the fixed vertices) in ascending label.  label[p] is the label stored at
+// position p, pos its inverse.
+void patch_major(const Mesh &M, const Mesh::TBPlan &P, std::vector<int32_t> &label, std::vector<int32_t> &pos) {
+    const int32_t n = M.n;
+    label.assign(size_t(n), -1);
+    pos.assign(size_t(n), -1);
+    for (int32_t t = 0; t < P.tiles; ++t) {
+        const int32_t nown = P.tile_ptr[size_t(t) + 1] - P.tile_ptr[size_t(t)];
+        for (int32_t i = 0; i < nown; ++i) {
+            const int32_t v = P.halo[size_t(P.halo_ptr[size_t(t)]) + size_t(i)];
+            const int32_t p = P.tile_ptr[size_t(t)] + i;
+            if (v < 0 || v >= n || p >= n || pos[size_t(v)] >= 0) fail(LMS_ERR_STATE, "patch plan: own rows");
+            label[size_t(p)] = v;
+            pos[size_t(v)] = p;
+        }
+    }
+    int32_t next = P.tiles > 0 ? P.tile_ptr[size_t(P.tiles)] : 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (pos[size_t(v)] < 0) {
+            if (!M.fixed[size_t(v)]) fail(LMS_ERR_STATE, "patch plan: a free row no tile owns");
+            label[size_t(next)] = v;
+            pos[size_t(v)] = next++;
+        }
+    if (next != n) fail(LMS_ERR_STATE, "patch plan: positions");
+}
+
 // Build (host) and upload the temporal-blocking plan of variant shape t.
 const DeviceState::TBDev &ensure_tb(DeviceState &d, Mesh &M, const TBShape &t) {
     if (const DeviceState::TBDev *h = find_tb(d, t)) return *h;
@@ -615,7 +646,16 @@ const DeviceState::TBDev &ensure_tb(DeviceState &d, Mesh &M, const TBShape &t) {
     h.tile_ptr = upload(&d, P.tile_ptr);
     h.ring = upload(&d, P.ring);
     h.halo_ptr = upload(&d, P.halo_ptr);
-    h.halo = upload(&d, P.halo);
+    if (h.patches && P.fits) {
+        std::vector<int32_t> label, pos;
+        patch_major(M, P, label, pos);
+        std::vector<int32_t> halo(P.halo.size());
+        for (size_t j = 0; j < halo.size(); ++j) halo[j] = pos[size_t(P.halo[j])];
+        h.halo = upload(&d, halo);
+        h.pm_label = upload(&d, label);
+    } else {
+        h.halo = upload(&d, P.halo);
+    }
     h.lidx_ptr = upload(&d, P.lidx_ptr);
     h.lidx = upload(&d, P.lidx);
     d.tbs.push_back(h);
@@ -640,7 +680,15 @@ bool ensure_tbq(DeviceState &d, Mesh &M, const TBShape &t) {
     if (!h->q_fits) return false;
     h->qtri_ptr = upload(&d, P->qtri_ptr);
     h->qtri = upload(&d, P->qtri);
-    h->qc_ids = upload(&d, P->qc_ids);
+    if (h->patches) {
+        std::vector<int32_t> label, pos;
+        patch_major(M, *P, label, pos);
+        std::vector<int32_t> ids(P->qc_ids.size());
+        for (size_t j = 0; j < ids.size(); ++j) ids[j] = pos[size_t(P->qc_ids[j])];
+        h->qc_ids = upload(&d, ids);
+    } else {
+        h->qc_ids = upload(&d, P->qc_ids);
+    }
     h->qc_w = upload(&d, P->qc_w);
     h->n_qc = int64_t(P->qc_w.size());
     h->qpart = upload(&d, std::vector<double>(size_t(t.k) * size_t(std::max(h->tiles, 1)), 0.0));
@@ -721,6 +769,7 @@ void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T>
         fail(LMS_ERR_STATE, "temporally blocked pass: separate outputs need both arrays and no quality");
     if (h->u_max > t.bs * t.r || size_t(h->l_max) * sizeof(vec2_t<T>) > size_t(64) * 1024)
         fail(LMS_ERR_STATE, "temporally blocked plan does not fit the variant");
+    if (h->patches && !h->pm_label) fail(LMS_ERR_STATE, "patch plan without its patch order");
     if (h->tiles == 0) return;
     const size_t lds = size_t(h->l_max) * sizeof(vec2_t<T>);
     switch (cfg) {
@@ -729,11 +778,11 @@ void launch_tb_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_t<T>
         if (qual)                                                                                              \
             k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, true, g != 0><<<h->tiles, bs, lds, s>>>(               \
                 h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, nullptr,        \
-                nullptr, h->qtri_ptr, h->qtri, h->qpart, d.st, max_iters);                                     \
+                nullptr, h->pm_label, h->qtri_ptr, h->qtri, h->qpart, d.st, max_iters);                        \
         else                                                                                                   \
             k_jacobi_tb<T, bs, w, r, map, ts, kk, lcap, false, g != 0><<<h->tiles, bs, lds, s>>>(              \
                 h->tile_ptr, h->ring, k, h->halo_ptr, h->halo, h->lidx_ptr, h->lidx, src, dst, ox, oy,         \
-                nullptr, nullptr, nullptr, nullptr, 0);                                                        \
+                h->pm_label, nullptr, nullptr, nullptr, nullptr, 0);                                           \
         break;
         LMS_TB_CONFIGS(TB)
 #undef TB
@@ -748,6 +797,8 @@ void launch_sweep2_cfg(int cfg, const DeviceState &d, const Mesh &M, const vec2_
     const int64_t n = M.n;
     if (is_tb_config(cfg)) {
         if (st) fail(LMS_ERR_STATE, "temporally blocked variants do not run under the stopping rule");
+        // a patch variant keeps its copies in patch order, which this caller's do not follow
+        if (tb_shape(cfg).g) fail(LMS_ERR_STATE, "patch variants run only in their own passes");
         launch_tb_cfg<T>(cfg, d, M, src, dst, 1, s);
         return;
     }
@@ -1672,8 +1723,28 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         d.io_x = x;
         d.io_y = y;
     }
-    auto pack = [&](hipStream_t cs) { k_pack<T><<<nb, 256, 0, cs>>>(x, y, A, in_place ? nullptr : B, M.n); };
-    auto unpack = [&](const vec2_t<T> *src, hipStream_t cs) { k_unpack<T><<<nb, 256, 0, cs>>>(src, x, y, M.n); };
+    // the variant whose passes run this call, when they are temporally
+    // blocked: a patch variant keeps the working copies in its patch order
+    const int fq = !colour && o.check_quality && small_rows == 0 ? fused_stop_cfg<T>(d, M) : -1;
+    const int layout_cfg = small_rows > 0 ? -1 : tb >= 0 ? tb : fq;
+    const int32_t *pm = nullptr;
+    if (layout_cfg >= 0 && tb_shape(layout_cfg).g) {
+        const DeviceState::TBDev *lh = find_tb(d, tb_shape(layout_cfg));
+        if (!lh || !lh->pm_label) fail(LMS_ERR_STATE, "patch variant without its patch order");
+        pm = lh->pm_label;
+    }
+    auto pack = [&](hipStream_t cs) {
+        if (pm)
+            k_pack_pm<T><<<nb, 256, 0, cs>>>(x, y, pm, A, in_place ? nullptr : B, M.n);
+        else
+            k_pack<T><<<nb, 256, 0, cs>>>(x, y, A, in_place ? nullptr : B, M.n);
+    };
+    auto unpack = [&](const vec2_t<T> *src, hipStream_t cs) {
+        if (pm)
+            k_unpack_pm<T><<<nb, 256, 0, cs>>>(src, pm, x, y, M.n);
+        else
+            k_unpack<T><<<nb, 256, 0, cs>>>(src, x, y, M.n);
+    };
     if (!io_in_graph) {
         pack(s);
         launch_check();
@@ -1763,7 +1834,7 @@ void smooth_packed(Mesh &M, DeviceState &d, T *x, T *y, lms_precision p, lms_sch
         in_b = !in_place && K % 2 == 1;
         r.stopped_by = LMS_STOP_MAX_ITERS;
         r.q0 = r.q_final = r.last_dq = std::numeric_limits<double>::quiet_NaN();
-    } else if (const int fq = colour ? -1 : fused_stop_cfg<T>(d, M); fq >= 0) {
+    } else if (fq >= 0) {
         // stopping rule with the quality fused into the sweep passes: each
         // pass evaluates the states it sweeps from; a stop inside a pass is
         // reached again from the pass's source copy

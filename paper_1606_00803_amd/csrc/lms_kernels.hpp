@@ -401,6 +401,32 @@ __global__ __launch_bounds__(256) void k_pack(const T *__restrict__ x, const T *
     if (b) b[i] = v;
 }
 
+// The same in patch order: position i of the working copies holds label[i].
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_pm(const T *__restrict__ x, const T *__restrict__ y,
+                                                 const int32_t *__restrict__ label, vec2_t<T> *__restrict__ a,
+                                                 vec2_t<T> *__restrict__ b, int32_t n) {
+    const int32_t i = int32_t(blockIdx.x) * 256 + int32_t(threadIdx.x);
+    if (i >= n) return;
+    const int32_t v = label[i];
+    vec2_t<T> p;
+    p.x = x[v];
+    p.y = y[v];
+    a[i] = p;
+    if (b) b[i] = p;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack_pm(const vec2_t<T> *__restrict__ a, const int32_t *__restrict__ label,
+                                                   T *__restrict__ x, T *__restrict__ y, int32_t n) {
+    const int32_t i = int32_t(blockIdx.x) * 256 + int32_t(threadIdx.x);
+    if (i >= n) return;
+    const vec2_t<T> p = a[i];
+    const int32_t v = label[i];
+    x[v] = p.x;
+    y[v] = p.y;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(const vec2_t<T> *__restrict__ a, T *__restrict__ x,
                                                 T *__restrict__ y, int32_t n) {
@@ -628,13 +654,16 @@ __device__ __forceinline__ double block_sum(double v, double *s_red);
 // size), KP (the plan's depth) and LCAP (its staging cap) name the variant
 // whose plan the kernel reads; the tiles themselves come from tile_ptr.
 //
-// G (patch tiles): the tile's own rows are not a range but the first nown
-// entries of its staged-row list (halo_ptr/halo then cover every staged row),
-// read and written through it.
+// G (patch tiles): the working copies are stored patch by patch (position p
+// holds label pm_label[p]): tile t's own rows are positions tile_ptr[t] ..
+// tile_ptr[t+1]-1, read and written as one contiguous run, and its staged-row
+// list (halo_ptr/halo, in positions) starts with those own rows, then its
+// rings.  Range tiles store rows by label (pm_label null) and list only their
+// rings.
 //
 // ox, oy (non-null only for the last pass of a fixed-K call without quality):
-// the last sweep writes the own free rows to these separate x and y arrays
-// instead of dst, so no unpack of dst follows.
+// the last sweep writes the own free rows to these separate x and y arrays,
+// by label, instead of dst, so no unpack of dst follows.
 //
 // QUAL (the stopping rule, Section 5.1): the pass also evaluates the quality
 // (Section 3.2) of each state it starts a sweep from.  Before sweep j+1 the
@@ -652,6 +681,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
                                                   const uint16_t *__restrict__ lidx,
                                                   const vec2_t<T> *__restrict__ src, vec2_t<T> *__restrict__ dst,
                                                   T *__restrict__ ox, T *__restrict__ oy,
+                                                  const int32_t *__restrict__ pm_label,
                                                   const int64_t *__restrict__ qtri_ptr,
                                                   const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
                                                   const StopState *__restrict__ st, int32_t max_iters) {
@@ -668,7 +698,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     }
     const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
     const int tid = int(threadIdx.x);
-    const int32_t b = G ? 0 : tile_ptr[tile];
+    const int32_t b = tile_ptr[tile];  // first own row (a position, for patches)
     static_assert(KP >= 1 && KP <= 8 && TS > 0 && LCAP > 0, "plan shape");
     const int32_t *rc = ring + int64_t(tile) * (KP + 1);
     const int32_t nown = rc[0], nload = rc[k > 0 ? k : 1], nupd = k > 0 ? rc[k - 1] : 0;
@@ -701,10 +731,9 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             for (int q = 0; q < W / 2; ++q) wd[r][q] = 0xFFFFFFFFu;
         }
     }
-    if constexpr (!G)
-        for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
-    const int32_t g0 = G ? 0 : nown;  // first staged row read through the list
-    stage_rows<T, BS>(halo + hb, nload - g0, src, sp, g0, tid);
+    for (int32_t i = tid; i < nown; i += BS) sp[i] = src[b + i];
+    // the rings, through the list (which, for patches, starts with the own rows)
+    stage_rows<T, BS>(halo + hb + (G ? nown : 0), nload - nown, src, sp, nown, tid);
     __syncthreads();
     const int32_t passes = QUAL && k == 0 ? 1 : k;
     for (int32_t j = 1; j <= passes; ++j) {
@@ -751,21 +780,22 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             }
         }
         if (j == k) {
-            int32_t vid[R];
+            if (ox) {
+                int32_t lab[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r)  // ids of the own rows, loads in flight together
-                vid[r] = G ? halo[hb + min(tid + BS * r, nown - 1)] : b + tid + BS * r;
+                for (int r = 0; r < R; ++r)  // labels of the own rows, loads in flight together
+                    lab[r] = G ? pm_label[b + min(tid + BS * r, nown - 1)] : b + tid + BS * r;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (w[r]) {
-                    const int32_t v = vid[r];
-                    if (ox) {
-                        ox[v] = o[r].x;
-                        oy[v] = o[r].y;
-                    } else {
-                        dst[v] = o[r];
+                for (int r = 0; r < R; ++r)
+                    if (w[r]) {
+                        ox[lab[r]] = o[r].x;
+                        oy[lab[r]] = o[r].y;
                     }
-                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (w[r]) dst[b + tid + BS * r] = o[r];
+            }
         } else {
             __syncthreads();
 #pragma unroll
