@@ -718,11 +718,14 @@ struct TBPart {
 
 }  // namespace
 
-// Patches: seeds in ascending label order; from each free row not yet
-// taken, take up to ts free rows not yet taken, in breadth-first order over
-// the adjacency (one pass over the mesh; a patch may reach rows of any
-// label, which gathers the scattered end of an ordering into the patches
-// around it).  Cached per tile size until the plans are dropped.
+// Patches: from a seed, take up to ts free rows not yet taken, in
+// breadth-first order over the adjacency.  The next seed is the first row,
+// in the order found, that borders a finished patch and is still free, so
+// patches grow outwards from those before them and leave few fragments
+// behind them whatever the labels; a component with no such row starts at
+// its lowest free label.  A patch may reach rows of any label, which
+// gathers the scattered end of an ordering into the patches around it.
+// Cached per tile size until the plans are dropped.
 const Mesh::Patches &patch_set(Mesh &M, int32_t ts) {
     for (const auto &q : M.patch_sets)
         if (q.ts == ts && q.version == M.version) return q;
@@ -732,17 +735,32 @@ const Mesh::Patches &patch_set(Mesh &M, int32_t ts) {
     q.patch_ptr.assign(1, 0);
     resize_or_fail(q.patch_rows, size_t(M.n_free));
     q.patch_rows.clear();
-    std::vector<uint8_t> taken(size_t(n), 0);
-    std::vector<int32_t> grow;
-    for (int32_t seed = 0; seed < n; ++seed) {
-        if (M.fixed[size_t(seed)] || taken[size_t(seed)]) continue;
+    std::vector<uint8_t> taken(size_t(n), 0), queued(size_t(n), 0);
+    std::vector<int32_t> grow, border;  // border holds each row once at most
+    size_t border_head = 0;
+    int32_t lowest = 0;
+    auto free_row = [&](int32_t v) { return !M.fixed[size_t(v)] && !taken[size_t(v)]; };
+    for (;;) {
+        int32_t seed = -1;
+        while (border_head < border.size()) {
+            const int32_t c = border[border_head++];
+            if (free_row(c)) {
+                seed = c;
+                break;
+            }
+        }
+        if (seed < 0) {
+            while (lowest < n && !free_row(lowest)) ++lowest;
+            if (lowest == n) break;
+            seed = lowest;
+        }
         grow.assign(1, seed);
         taken[size_t(seed)] = 1;
         for (size_t h = 0; h < grow.size() && h < size_t(ts); ++h) {
             const int32_t v = grow[h];
             for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
                 const int32_t u = M.col[size_t(j)];
-                if (!M.fixed[size_t(u)] && !taken[size_t(u)]) {
+                if (free_row(u)) {
                     taken[size_t(u)] = 1;
                     grow.push_back(u);
                 }
@@ -750,6 +768,14 @@ const Mesh::Patches &patch_set(Mesh &M, int32_t ts) {
         }
         for (size_t i = size_t(ts); i < grow.size(); ++i) taken[size_t(grow[i])] = 0;  // give the rest back
         grow.resize(std::min(grow.size(), size_t(ts)));
+        for (const int32_t v : grow)
+            for (int32_t j = M.row_ptr[v]; j < M.row_ptr[v + 1]; ++j) {
+                const int32_t u = M.col[size_t(j)];
+                if (free_row(u) && !queued[size_t(u)]) {
+                    queued[size_t(u)] = 1;
+                    border.push_back(u);
+                }
+            }
         q.patch_rows.insert(q.patch_rows.end(), grow.begin(), grow.end());
         q.patch_ptr.push_back(int64_t(q.patch_rows.size()));
     }
