@@ -12,6 +12,7 @@
 
 #include <cstdint>
 
+#include "lms_divide.hpp"
 #include "lms_internal.hpp"
 
 namespace lms {
@@ -361,6 +362,41 @@ __device__ __forceinline__ int lds_row_sum(const vec2_t<T> *sp, Slot slot, T &ax
     return c;
 }
 
+// The same from byte offsets into sp, two per word (offset 2q in the low half
+// of word q, 0xFFFF past the row's end): the address is the offset itself.
+template <typename T, int W>
+__device__ __forceinline__ int lds_row_sum_bytes(const vec2_t<T> *sp, const uint32_t (&wd)[W / 2], T &ax, T &ay) {
+    const unsigned char *base = reinterpret_cast<const unsigned char *>(sp);
+    T sx = T(0), sy = T(0);
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        const uint32_t off = (wd[q / 2] >> (16 * (q % 2))) & 0xFFFFu;
+        if (off != 0xFFFFu) {
+            const vec2_t<T> p = *reinterpret_cast<const vec2_t<T> *>(base + off);
+            sx += p.x;
+            sy += p.y;
+            ++c;
+        }
+    }
+    ax = sx;
+    ay = sy;
+    return c;
+}
+
+// Slots packed two per word -> byte offsets into an array of vec2_t<T>
+// (0xFFFF stays): a staging area of at most 4096 rows keeps every offset
+// below 0xFFFF.
+template <typename T, int W>
+__device__ __forceinline__ void slots_to_bytes(uint32_t (&wd)[W / 2]) {
+    constexpr uint32_t s = uint32_t(sizeof(vec2_t<T>));
+#pragma unroll
+    for (int q = 0; q < W / 2; ++q) {
+        const uint32_t lo = wd[q] & 0xFFFFu, hi = wd[q] >> 16;
+        wd[q] = (lo == 0xFFFFu ? lo : lo * s) | ((hi == 0xFFFFu ? hi : hi * s) << 16);
+    }
+}
+
 // The same for slots packed two per word (slot 2q in the low half of word q).
 template <typename T, int W>
 __device__ __forceinline__ int lds_row_sum_words(const vec2_t<T> *sp, const uint32_t (&wd)[W / 2], T &ax, T &ay) {
@@ -588,7 +624,7 @@ __global__ __launch_bounds__(TS) void k_jacobi_halo(const int32_t *__restrict__ 
                                                     const vec2_t<T> *__restrict__ src,
                                                     vec2_t<T> *__restrict__ dst, int32_t n,
                                                     const StopState *__restrict__ st) {
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     vec2_t<T> *stage = reinterpret_cast<vec2_t<T> *>(lds_raw);
     if (st && st->done) return;
     const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
@@ -665,6 +701,14 @@ __device__ __forceinline__ double block_sum(double v, double *s_red);
 // the last sweep writes the own free rows to these separate x and y arrays,
 // by label, instead of dst, so no unpack of dst follows.
 //
+// float64: a row's slots are kept as byte offsets and decoded again in every
+// sweep, and the quotient comes from div_by_count with 1/c from an LDS
+// table.  The compiler would otherwise keep every slot's address in its own
+// register across the sweeps, which takes a variant with three rows per
+// thread past 64 registers, so that only one 1024-thread workgroup fits on a
+// CU; this way it holds ~50 and two fit.  float32 rows fit either way and
+// keep the hoisted addresses and the plain division, which measured faster.
+//
 // QUAL (the stopping rule, Section 5.1): the pass also evaluates the quality
 // (Section 3.2) of each state it starts a sweep from.  Before sweep j+1 the
 // own rows and ring 1 hold state s+j, and every triangle of the tile (those
@@ -688,10 +732,15 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     static_assert(W % 4 == 0, "padded width must be a multiple of 4");
     constexpr int QR = 2;     // triangle records per thread held in registers
     constexpr int NRCP = 64;  // 1/c for triangle counts c = 1..NRCP from a table (the same division)
-    extern __shared__ unsigned char lds_raw[];
+    constexpr bool BYTES = sizeof(T) == 8;  // slots as byte offsets, quotient by div_by_count
+    static_assert(!BYTES || LCAP * sizeof(vec2_t<T>) <= 65536, "byte offsets fit 16 bits");
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double s_red[BS / 64];
     __shared__ double s_rcp[QUAL ? NRCP + 1 : 1];
+    __shared__ T s_inv[BYTES ? W + 1 : 1];  // RN(1/c), c = 1..W
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
+    if constexpr (BYTES)
+        if (threadIdx.x <= W) s_inv[threadIdx.x] = threadIdx.x == 0 ? T(0) : T(1) / T(int(threadIdx.x));
     if constexpr (QUAL) {
         if (st->done) return;
         k = min(KP, max_iters - st->swept);
@@ -726,6 +775,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
         const int32_t i = tid + BS * r;
         if (i < nupd) {
             load_slot_words<W>(lidx + (lb + i) * W, wd[r]);
+            if constexpr (BYTES) slots_to_bytes<T, W>(wd[r]);
         } else {
 #pragma unroll
             for (int q = 0; q < W / 2; ++q) wd[r][q] = 0xFFFFFFFFu;
@@ -761,6 +811,14 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             if (k == 0) break;
         }
         const int32_t m = rc[k - j];  // rows updated by this sweep
+        if constexpr (BYTES) {
+            // the words are opaque to the compiler here, so it decodes them in
+            // each sweep instead of holding W addresses per row
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int q = 0; q < W / 2; ++q) asm volatile("" : "+v"(wd[r][q]));
+        }
         vec2_t<T> o[R];
         bool w[R];
 #pragma unroll
@@ -772,11 +830,17 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
             if (BS * r >= m) continue;  // the same for the whole workgroup
             if (i >= m) continue;
             T ax, ay;
-            const int c = lds_row_sum_words<T, W>(sp, wd[r], ax, ay);
+            const int c = BYTES ? lds_row_sum_bytes<T, W>(sp, wd[r], ax, ay) : lds_row_sum_words<T, W>(sp, wd[r], ax, ay);
             w[r] = c > 0;
             if (c > 0) {
-                o[r].x = ax / T(c);
-                o[r].y = ay / T(c);
+                if constexpr (BYTES) {
+                    const T y = s_inv[c];
+                    o[r].x = div_by_count(ax, T(c), y);
+                    o[r].y = div_by_count(ay, T(c), y);
+                } else {
+                    o[r].x = ax / T(c);
+                    o[r].y = ay / T(c);
+                }
             }
         }
         if (j == k) {
@@ -820,7 +884,7 @@ __global__ __launch_bounds__(256) void k_small_meshes(const int64_t *__restrict_
                                                       vec2_t<T> *__restrict__ a, vec2_t<T> *__restrict__ b,
                                                       int32_t K) {
     static_assert(W % 2 == 0, "slots are packed in pairs");
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
     const int64_t vb = v_off[blockIdx.x];
     const int32_t nv = int32_t(v_off[blockIdx.x + 1] - vb);
@@ -950,7 +1014,7 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
                                                      const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
                                                      int32_t max_iters) {
     static_assert(KP >= 1 && KP <= 8, "sweeps per pass");
-    extern __shared__ unsigned char lds_raw[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double s_red[BS / 64];
     __shared__ double s_rcp[QUAL ? 65 : 1];
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);

@@ -294,6 +294,24 @@ def test_no_kernel_spills_to_scratch(source):
     assert not spilled, spilled
 
 
+def test_count_division_is_ieee_division(tmp_path):
+    # the sweep kernels' quotient (a multiplication and two fused
+    # multiply-adds from a table of 1/c) against IEEE division, bit for bit,
+    # in float64 and float32, on the host
+    import subprocess
+    from paper_1606_00803_amd import build as b
+    exe = str(tmp_path / "division_check")
+    cmd = [b._hipcc(), "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", f"--offload-arch={b.ARCH}",
+           "-Wno-unused-command-line-argument", f"-I{b.CSRC}", os.path.join(os.path.dirname(__file__),
+                                                                         "division_check.hip"), "-o", exe]
+    out = subprocess.run(cmd, capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr[-2000:]
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    print(run.stdout)
+    assert run.returncode == 0, run.stdout[-2000:]
+    assert "float64: " in run.stdout and "float32: " in run.stdout
+
+
 @pytest.mark.parametrize("kind", ["ori", "bfs", "rdr", "random"])
 def test_reuse_profile_matches_oracle(kind):
     from oracle import reuse as ore
