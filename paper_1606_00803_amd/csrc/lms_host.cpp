@@ -1034,18 +1034,18 @@ namespace {
 // passes.  Every triangle with a free corner belongs to the tile owning its
 // smallest free corner (tile_of(v)); slot_of(tile, v) gives a staged corner's
 // slot (every corner is staged: the others are neighbours of that free corner).
-// Records: slots a | b<<16, c | |T(a)|<<16, |T(b)| | |T(c)|<<16.  Triangles
+// Records, four words each: slots a | b<<16, slot c, then the triangle's
+// weight w_t (the double the quality pass uses, low word first).  Triangles
 // with all corners fixed are listed apart with their weights.  False when a
-// triangle count exceeds 16 bits.
+// slot does not fit 16 bits.
 template <class TileOf, class SlotOf>
 bool tile_quality_records(const Mesh &M, int32_t tiles, TileOf tile_of, SlotOf slot_of,
                           std::vector<int64_t> &qtri_ptr, std::vector<uint32_t> &qtri, std::vector<int32_t> &qc_ids,
                           std::vector<double> &qc_w) {
     const int64_t T = M.T;
-    for (int32_t v = 0; v < M.n; ++v)
-        if (M.tcount0[size_t(v)] > 0xFFFF) return false;
     std::vector<int32_t> owner(size_t(T), -1);
-    std::vector<uint32_t> rec(size_t(3) * size_t(T), 0u);
+    std::vector<uint32_t> rec(size_t(4) * size_t(T), 0u);
+    std::atomic<bool> fits{true};
     parallel_runs(T, host_threads(T / 256), [&](int, int64_t first, int64_t last) {
         for (int64_t t = first; t < last; ++t) {
             const int32_t c3[3] = {M.ta[size_t(t)], M.tb[size_t(t)], M.tc[size_t(t)]};
@@ -1054,19 +1054,23 @@ bool tile_quality_records(const Mesh &M, int32_t tiles, TileOf tile_of, SlotOf s
                 if (!M.fixed[size_t(v)] && (own < 0 || v < own)) own = v;
             if (own < 0) continue;
             const int32_t tile = tile_of(own);
-            uint32_t slot[3], cnt[3];
+            uint32_t slot[3];
             for (int q = 0; q < 3; ++q) {
                 const int32_t sl = slot_of(tile, c3[q]);
                 if (sl < 0) fail(LMS_ERR_STATE, "quality plan: corner not staged");
-                slot[q] = uint32_t(sl);
-                cnt[q] = uint32_t(M.tcount0[size_t(M.new2old[size_t(c3[q])])]);
+                if (sl > 0xFFFF) fits = false;
+                slot[q] = uint32_t(sl) & 0xFFFFu;
             }
             owner[size_t(t)] = tile;
-            rec[size_t(3 * t)] = slot[0] | (slot[1] << 16);
-            rec[size_t(3 * t + 1)] = slot[2] | (cnt[0] << 16);
-            rec[size_t(3 * t + 2)] = cnt[1] | (cnt[2] << 16);
+            uint32_t wbits[2];
+            std::memcpy(wbits, &M.tw[size_t(t)], sizeof(double));
+            rec[size_t(4 * t)] = slot[0] | (slot[1] << 16);
+            rec[size_t(4 * t + 1)] = slot[2];
+            rec[size_t(4 * t + 2)] = wbits[0];
+            rec[size_t(4 * t + 3)] = wbits[1];
         }
     });
+    if (!fits) return false;
     // group by tile (stable: ascending triangle index inside a tile)
     qtri_ptr.assign(size_t(tiles) + 1, 0);
     qc_ids.clear();
@@ -1080,16 +1084,23 @@ bool tile_quality_records(const Mesh &M, int32_t tiles, TileOf tile_of, SlotOf s
         }
     }
     for (int32_t i = 0; i < tiles; ++i) qtri_ptr[size_t(i) + 1] += qtri_ptr[size_t(i)];
-    resize_or_fail(qtri, size_t(3) * size_t(qtri_ptr.back()));
+    resize_or_fail(qtri, size_t(4) * size_t(qtri_ptr.back()));
     std::vector<int64_t> fill(qtri_ptr.begin(), qtri_ptr.end() - 1);
     for (int64_t t = 0; t < T; ++t) {
         const int32_t o = owner[size_t(t)];
         if (o < 0) continue;
         const int64_t at = fill[size_t(o)]++;
-        for (int q = 0; q < 3; ++q) qtri[size_t(3 * at + q)] = rec[size_t(3 * t + q)];
+        for (int q = 0; q < 4; ++q) qtri[size_t(4 * at + q)] = rec[size_t(4 * t + q)];
     }
     if (qtri_ptr.back() + int64_t(qc_w.size()) != T) fail(LMS_ERR_STATE, "quality plan: triangle count");
     return true;
+}
+
+// A record's slots lie below `staged` and its weight is positive and finite.
+bool quality_record_ok(const uint32_t *w, uint32_t staged) {
+    double wt;
+    std::memcpy(&wt, w + 2, sizeof(double));
+    return (w[0] & 0xFFFFu) < staged && (w[0] >> 16) < staged && w[1] < staged && wt > 0.0 && std::isfinite(wt);
 }
 
 }  // namespace
@@ -1131,15 +1142,12 @@ void tb_quality_plan(const Mesh &M, Mesh::TBPlan &P) {
     };
     P.q_fits = tile_quality_records(M, P.tiles, tile_of, slot_of, P.qtri_ptr, P.qtri, P.qc_ids, P.qc_w);
     if (!P.q_fits) return;
-    // self-check: slots inside own + ring 1, counts non-zero
+    // self-check: slots inside own + ring 1, weights positive and finite
     for (int32_t i = 0; i < P.tiles; ++i) {
         const int32_t *r = P.ring.data() + size_t(i) * size_t(k + 1);
-        for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t) {
-            const uint32_t w0 = P.qtri[size_t(3 * t)], w1 = P.qtri[size_t(3 * t + 1)], w2 = P.qtri[size_t(3 * t + 2)];
-            if ((w0 & 0xFFFFu) >= uint32_t(r[1]) || (w0 >> 16) >= uint32_t(r[1]) || (w1 & 0xFFFFu) >= uint32_t(r[1]) ||
-                (w1 >> 16) == 0 || (w2 & 0xFFFFu) == 0 || (w2 >> 16) == 0)
+        for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t)
+            if (!quality_record_ok(P.qtri.data() + 4 * t, uint32_t(r[1])))
                 fail(LMS_ERR_STATE, "quality plan: record out of range");
-        }
     }
 }
 
@@ -1183,12 +1191,8 @@ void mc_quality_plan(const Mesh &M, Mesh::MCPlan &P) {
     for (int32_t i = 0; i < P.tiles; ++i) {
         const uint32_t nst = uint32_t(P.halo_ptr[size_t(i) + 1] - P.halo_ptr[size_t(i)]) +
                              uint32_t(P.patches ? 0 : P.tile_ptr[size_t(i) + 1] - P.tile_ptr[size_t(i)]);
-        for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t) {
-            const uint32_t w0 = P.qtri[size_t(3 * t)], w1 = P.qtri[size_t(3 * t + 1)], w2 = P.qtri[size_t(3 * t + 2)];
-            if ((w0 & 0xFFFFu) >= nst || (w0 >> 16) >= nst || (w1 & 0xFFFFu) >= nst || (w1 >> 16) == 0 ||
-                (w2 & 0xFFFFu) == 0 || (w2 >> 16) == 0)
-                fail(LMS_ERR_STATE, "quality plan: record out of range");
-        }
+        for (int64_t t = P.qtri_ptr[size_t(i)]; t < P.qtri_ptr[size_t(i) + 1]; ++t)
+            if (!quality_record_ok(P.qtri.data() + 4 * t, nst)) fail(LMS_ERR_STATE, "quality plan: record out of range");
     }
 }
 

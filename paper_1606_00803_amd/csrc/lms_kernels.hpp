@@ -671,6 +671,16 @@ __device__ __forceinline__ void load_slot_words(const uint16_t *__restrict__ row
 }
 
 __device__ __forceinline__ double tri_quality(double xa, double ya, double xb, double yb, double xc, double yc);
+
+// w_t q_t of one triangle of a tile from its 16-byte record (slots a | b<<16,
+// slot c, then w_t = 1/|T(a)| + 1/|T(b)| + 1/|T(c)| as a double, the value
+// the host computed for the quality pass): the corners come from LDS.
+template <typename T>
+__device__ __forceinline__ double tri_record_term(const vec2_t<T> *sp, const u32x4 &w) {
+    const vec2_t<T> pa = sp[w.x & 0xFFFFu], pb = sp[w.x >> 16], pc = sp[w.y];
+    const double q = tri_quality(double(pa.x), double(pa.y), double(pb.x), double(pb.y), double(pc.x), double(pc.y));
+    return q * __hiloint2double(int(w.w), int(w.z));
+}
 template <int BS>
 __device__ __forceinline__ double block_sum(double v, double *s_red);
 
@@ -730,13 +740,11 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
                                                   const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
                                                   const StopState *__restrict__ st, int32_t max_iters) {
     static_assert(W % 4 == 0, "padded width must be a multiple of 4");
-    constexpr int QR = 2;     // triangle records per thread held in registers
-    constexpr int NRCP = 64;  // 1/c for triangle counts c = 1..NRCP from a table (the same division)
+    constexpr int QR = 2;  // triangle records per thread held in registers
     constexpr bool BYTES = sizeof(T) == 8;  // slots as byte offsets, quotient by div_by_count
     static_assert(!BYTES || LCAP * sizeof(vec2_t<T>) <= 65536, "byte offsets fit 16 bits");
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double s_red[BS / 64];
-    __shared__ double s_rcp[QUAL ? NRCP + 1 : 1];
     __shared__ T s_inv[BYTES ? W + 1 : 1];  // RN(1/c), c = 1..W
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
     if constexpr (BYTES)
@@ -752,21 +760,16 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     const int32_t *rc = ring + int64_t(tile) * (KP + 1);
     const int32_t nown = rc[0], nload = rc[k > 0 ? k : 1], nupd = k > 0 ? rc[k - 1] : 0;
     const int64_t hb = halo_ptr[tile], lb = lidx_ptr[tile];
-    uint32_t qw[QUAL ? QR : 1][3];
+    u32x4 qw[QUAL ? QR : 1];
     int64_t qb = 0, qe = 0;
     if constexpr (QUAL) {
-        for (int c = tid; c <= NRCP; c += BS) s_rcp[c] = c == 0 ? 0.0 : 1.0 / double(c);
         qb = qtri_ptr[tile];
         qe = qtri_ptr[tile + 1];
 #pragma unroll
         for (int r = 0; r < QR; ++r) {
             const int64_t t = qb + tid + BS * r;
-            qw[r][0] = qw[r][1] = qw[r][2] = 0u;  // count 0: no triangle
-            if (t < qe) {
-                qw[r][0] = qtri[3 * t];
-                qw[r][1] = qtri[3 * t + 1];
-                qw[r][2] = qtri[3 * t + 2];
-            }
+            qw[r] = u32x4{0u, 0u, 0u, 0u};  // weight 0: no triangle
+            if (t < qe) qw[r] = reinterpret_cast<const u32x4 *>(qtri)[t];
         }
     }
     uint32_t wd[R][W / 2];
@@ -789,22 +792,13 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     for (int32_t j = 1; j <= passes; ++j) {
         if constexpr (QUAL) {
             // quality of state s+j-1: every triangle of the tile, from LDS
-            auto tri_term = [&](uint32_t w0, uint32_t w1, uint32_t w2) {
-                const vec2_t<T> pa = sp[w0 & 0xFFFFu], pb = sp[w0 >> 16], pc = sp[w1 & 0xFFFFu];
-                const double q = tri_quality(double(pa.x), double(pa.y), double(pb.x), double(pb.y), double(pc.x),
-                                             double(pc.y));
-                const uint32_t ca = w1 >> 16, cb = w2 & 0xFFFFu, cc = w2 >> 16;
-                const double ra = ca <= NRCP ? s_rcp[ca] : 1.0 / double(ca);
-                const double rb = cb <= NRCP ? s_rcp[cb] : 1.0 / double(cb);
-                const double rc = cc <= NRCP ? s_rcp[cc] : 1.0 / double(cc);
-                return q * (ra + rb + rc);
-            };
+            auto tri_term = [&](const u32x4 &w) { return tri_record_term<T>(sp, w); };
             double acc = 0.0;
 #pragma unroll
             for (int r = 0; r < QR; ++r)
-                if ((qw[r][1] >> 16) != 0u) acc += tri_term(qw[r][0], qw[r][1], qw[r][2]);
+                if (qw[r].w != 0u) acc += tri_term(qw[r]);
             for (int64_t t = qb + QR * BS + tid; t < qe; t += BS)
-                acc += tri_term(qtri[3 * t], qtri[3 * t + 1], qtri[3 * t + 2]);
+                acc += tri_term(reinterpret_cast<const u32x4 *>(qtri)[t]);
             const double sum = block_sum<BS>(acc, s_red);
             if (tid == 0) qpart[int64_t(j - 1) * gridDim.x + tile] = sum;
             __syncthreads();  // s_red is reused by the next state's sum
@@ -1016,13 +1010,9 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
     static_assert(KP >= 1 && KP <= 8, "sweeps per pass");
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double s_red[BS / 64];
-    __shared__ double s_rcp[QUAL ? 65 : 1];
     vec2_t<T> *sp = reinterpret_cast<vec2_t<T> *>(lds_raw);
     if (st && st->done) return;
-    if constexpr (QUAL) {
-        depth = min(1, max_iters - st->swept);
-        for (int c = int(threadIdx.x); c <= 64; c += BS) s_rcp[c] = c == 0 ? 0.0 : 1.0 / double(c);
-    }
+    if constexpr (QUAL) depth = min(1, max_iters - st->swept);
     const int tile = tile_of<MAP>(int(blockIdx.x), int(gridDim.x));
     const int tid = int(threadIdx.x);
     const int32_t b = tile_ptr[tile], nown = tile_ptr[tile + 1] - b;
@@ -1057,17 +1047,8 @@ __global__ __launch_bounds__(BS) void k_colour_tiles(const int32_t *__restrict__
     if constexpr (QUAL) {
         // quality of the source state: the tile's triangles, from LDS
         double acc = 0.0;
-        for (int64_t t = qtri_ptr[tile] + tid; t < qtri_ptr[tile + 1]; t += BS) {
-            const uint32_t w0 = qtri[3 * t], w1 = qtri[3 * t + 1], w2 = qtri[3 * t + 2];
-            const vec2_t<T> pa = sp[w0 & 0xFFFFu], pb = sp[w0 >> 16], pc = sp[w1 & 0xFFFFu];
-            const double q = tri_quality(double(pa.x), double(pa.y), double(pb.x), double(pb.y), double(pc.x),
-                                         double(pc.y));
-            const uint32_t ca = w1 >> 16, cb = w2 & 0xFFFFu, cc = w2 >> 16;
-            const double ra = ca <= 64 ? s_rcp[ca] : 1.0 / double(ca);
-            const double rb = cb <= 64 ? s_rcp[cb] : 1.0 / double(cb);
-            const double rc = cc <= 64 ? s_rcp[cc] : 1.0 / double(cc);
-            acc += q * (ra + rb + rc);
-        }
+        for (int64_t t = qtri_ptr[tile] + tid; t < qtri_ptr[tile + 1]; t += BS)
+            acc += tri_record_term<T>(sp, reinterpret_cast<const u32x4 *>(qtri)[t]);
         const double sum = block_sum<BS>(acc, s_red);
         if (tid == 0) qpart[tile] = sum;
         if (depth == 0) return;  // all sweeps done: the state was evaluated only

@@ -21,13 +21,15 @@
 // Prints one line per plan shape; exits 1 on any mismatch or library error.
 // With "plant", each plan is simulated from a copy in which one own row of
 // the first tile reads its own slot in place of its first neighbour, and the
-// first triangle record counts one triangle too many at its second corner:
+// weight of the first triangle record counts one triangle too many at its
+// second corner:
 // every fitting shape must then report mismatches and a large q_err (a check
 // of this checker).
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <fstream>
 #include <random>
 #include <string>
@@ -206,19 +208,26 @@ double quality_sum_direct(const Mesh &M, const std::vector<double> &x, const std
 }
 
 // The same sum from a plan's triangle records: each record names three
-// staging slots of its tile and the triangle counts of the three corners;
-// triangles with only fixed corners are listed apart with their weights.
+// staging slots of its tile and carries the triangle's weight (a double in
+// its last two words); triangles with only fixed corners are listed apart
+// with their weights.
+double record_weight(const uint32_t *w) {
+    double wt;
+    std::memcpy(&wt, w + 2, sizeof(double));
+    return wt;
+}
+
 template <class Plan, class RowOf>
 double quality_sum_plan(const Plan &P, RowOf row_of, const std::vector<double> &xc, const std::vector<double> &yc) {
     double total = 0.0;
     for (int32_t t = 0; t < P.tiles; ++t)
         for (int64_t i = P.qtri_ptr[size_t(t)]; i < P.qtri_ptr[size_t(t) + 1]; ++i) {
-            const uint32_t w0 = P.qtri[size_t(3 * i)], w1 = P.qtri[size_t(3 * i + 1)], w2 = P.qtri[size_t(3 * i + 2)];
-            const int32_t a = row_of(t, int32_t(w0 & 0xFFFFu)), b = row_of(t, int32_t(w0 >> 16)),
-                          c = row_of(t, int32_t(w1 & 0xFFFFu));
+            const uint32_t *w = P.qtri.data() + 4 * i;
+            const int32_t a = row_of(t, int32_t(w[0] & 0xFFFFu)), b = row_of(t, int32_t(w[0] >> 16)),
+                          c = row_of(t, int32_t(w[1]));
             const double q = tri_q(xc[size_t(a)], yc[size_t(a)], xc[size_t(b)], yc[size_t(b)], xc[size_t(c)],
                                    yc[size_t(c)]);
-            total += q * (1.0 / double(w1 >> 16) + 1.0 / double(w2 & 0xFFFFu) + 1.0 / double(w2 >> 16));
+            total += q * record_weight(w);
         }
     for (size_t i = 0; i < P.qc_w.size(); ++i) {
         const int32_t a = P.qc_ids[3 * i], b = P.qc_ids[3 * i + 1], c = P.qc_ids[3 * i + 2];
@@ -279,6 +288,22 @@ long check_relabel(const Mesh &M) {
         }
     bad += M.vt_ptr[n] != 3 * M.T;
     return bad;
+}
+
+// The planted weight: the first triangle record's weight as if its second
+// corner were in one triangle more.
+template <class Plan, class RowOf>
+void plant_weight(const Mesh &M, Plan &P, RowOf row_of) {
+    int32_t t0 = 0;
+    while (t0 < P.tiles && P.qtri_ptr[size_t(t0) + 1] == P.qtri_ptr[size_t(t0)]) ++t0;
+    if (t0 == P.tiles) return;
+    uint32_t *w = P.qtri.data() + 4 * P.qtri_ptr[size_t(t0)];
+    const int32_t rows[3] = {row_of(t0, int32_t(w[0] & 0xFFFFu)), row_of(t0, int32_t(w[0] >> 16)),
+                             row_of(t0, int32_t(w[1]))};
+    double c[3];
+    for (int q = 0; q < 3; ++q) c[q] = double(M.tcount0[size_t(M.new2old[size_t(rows[q])])]);
+    const double wt = 1.0 / c[0] + 1.0 / (c[1] + 1.0) + 1.0 / c[2];
+    std::memcpy(w + 2, &wt, sizeof(double));
 }
 
 // The planted mistakes: the first own row of tile 0 that has neighbours
@@ -392,12 +417,12 @@ int main(int argc, char **argv) {
                 if (P.fits) {
                     for (int d = 1; d <= P.k; ++d) bad += count_mismatches(tb_pass(M, P, p0, d), jacobi(M, p0, d));
                     lms::tb_quality_plan(M, P);
-                    if (planted && P.q_fits && !P.qtri.empty()) P.qtri[2] += 1u;
                     auto row_of = [&](int32_t t, int32_t sl) {
                         const int32_t nown = P.ring[size_t(t) * size_t(P.k + 1)];
                         if (P.patches) return P.halo[size_t(P.halo_ptr[size_t(t)] + sl)];
                         return sl < nown ? P.tile_ptr[size_t(t)] + sl : P.halo[size_t(P.halo_ptr[size_t(t)] + sl - nown)];
                     };
+                    if (planted && P.q_fits) plant_weight(M, P, row_of);
                     if (P.q_fits) qe = q_err(quality_sum_plan(P, row_of, xc, yc));
                 }
                 total_bad += bad;
@@ -417,12 +442,12 @@ int main(int argc, char **argv) {
                     for (int d = 1; d <= P.k; ++d)
                         bad += count_mismatches(mc_pass(M, P, p0, d), multicolour(M, p0, d));
                     lms::mc_quality_plan(M, P);
-                    if (planted && P.q_fits && !P.qtri.empty()) P.qtri[2] += 1u;
                     auto row_of = [&](int32_t t, int32_t sl) {
                         const int32_t nown = P.tile_ptr[size_t(t) + 1] - P.tile_ptr[size_t(t)];
                         if (P.patches) return P.halo[size_t(P.halo_ptr[size_t(t)] + sl)];
                         return sl < nown ? P.tile_ptr[size_t(t)] + sl : P.halo[size_t(P.halo_ptr[size_t(t)] + sl - nown)];
                     };
+                    if (planted && P.q_fits) plant_weight(M, P, row_of);
                     if (P.q_fits) qe = q_err(quality_sum_plan(P, row_of, xc, yc));
                 }
                 total_bad += bad;
