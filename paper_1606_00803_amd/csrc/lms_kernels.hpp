@@ -711,13 +711,14 @@ __device__ __forceinline__ double block_sum(double v, double *s_red);
 // the last sweep writes the own free rows to these separate x and y arrays,
 // by label, instead of dst, so no unpack of dst follows.
 //
-// float64: a row's slots are kept as byte offsets and decoded again in every
-// sweep, and the quotient comes from div_by_count with 1/c from an LDS
-// table.  The compiler would otherwise keep every slot's address in its own
-// register across the sweeps, which takes a variant with three rows per
-// thread past 64 registers, so that only one 1024-thread workgroup fits on a
-// CU; this way it holds ~50 and two fit.  float32 rows fit either way and
-// keep the hoisted addresses and the plain division, which measured faster.
+// float64, and the quality-fused form in either precision: a row's slots are
+// kept as byte offsets and decoded again in every sweep, and the quotient
+// comes from div_by_count with 1/c from an LDS table.  The compiler would
+// otherwise keep every slot's address in its own register across the sweeps,
+// which takes a variant with three rows per thread past 64 registers, so that
+// only one 1024-thread workgroup fits on a CU; this way it holds ~50 and two
+// fit.  Plain float32 rows fit either way and keep the hoisted addresses and
+// the plain division, which measured faster.
 //
 // QUAL (the stopping rule, Section 5.1): the pass also evaluates the quality
 // (Section 3.2) of each state it starts a sweep from.  Before sweep j+1 the
@@ -727,7 +728,8 @@ __device__ __forceinline__ double block_sum(double v, double *s_red);
 // from the device state: k = min(KP, max_iters - swept), and a pass of depth
 // 0 (all sweeps done) evaluates its source state only.
 template <typename T, int BS, int W, int R, int MAP, int TS, int KP, int LCAP, bool QUAL, bool G>
-__global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ tile_ptr,
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(QUAL && R <= 2 && BS == 1024 ? 8 : 1))) void
+k_jacobi_tb(const int32_t *__restrict__ tile_ptr,
                                                   const int32_t *__restrict__ ring, int32_t k,
                                                   const int64_t *__restrict__ halo_ptr,
                                                   const int32_t *__restrict__ halo,
@@ -740,8 +742,13 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
                                                   const uint32_t *__restrict__ qtri, double *__restrict__ qpart,
                                                   const StopState *__restrict__ st, int32_t max_iters) {
     static_assert(W % 4 == 0, "padded width must be a multiple of 4");
-    constexpr int QR = 2;  // triangle records per thread held in registers
-    constexpr bool BYTES = sizeof(T) == 8;  // slots as byte offsets, quotient by div_by_count
+    // the quality-fused form on 1024 threads and two rows per thread reads its
+    // triangle records from memory for every state and is held to 64
+    // registers, so that two workgroups fit on a CU; the others keep QR
+    // records per thread in registers
+    constexpr bool FIT2 = QUAL && R <= 2 && BS == 1024;
+    constexpr int QR = FIT2 ? 0 : 2;
+    constexpr bool BYTES = sizeof(T) == 8 || QUAL;  // slots as byte offsets, quotient by div_by_count
     static_assert(!BYTES || LCAP * sizeof(vec2_t<T>) <= 65536, "byte offsets fit 16 bits");
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double s_red[BS / 64];
@@ -760,7 +767,7 @@ __global__ __launch_bounds__(BS) void k_jacobi_tb(const int32_t *__restrict__ ti
     const int32_t *rc = ring + int64_t(tile) * (KP + 1);
     const int32_t nown = rc[0], nload = rc[k > 0 ? k : 1], nupd = k > 0 ? rc[k - 1] : 0;
     const int64_t hb = halo_ptr[tile], lb = lidx_ptr[tile];
-    u32x4 qw[QUAL ? QR : 1];
+    u32x4 qw[QUAL && QR > 0 ? QR : 1];
     int64_t qb = 0, qe = 0;
     if constexpr (QUAL) {
         qb = qtri_ptr[tile];
