@@ -290,6 +290,42 @@ long check_relabel(const Mesh &M) {
     return bad;
 }
 
+// Wrong entries of a patch set: free rows in no patch or in two, fixed rows
+// in a patch, patches over ts rows or empty, and patches whose rows are not
+// all reached from their first row over the adjacency inside the patch.
+long check_patches(const Mesh &M, const Mesh::Patches &ps, int ts) {
+    long bad = 0;
+    std::vector<int32_t> owner(size_t(M.n), -1);
+    const int32_t np = int32_t(ps.patch_ptr.size()) - 1;
+    for (int32_t p = 0; p < np; ++p) {
+        const int64_t b = ps.patch_ptr[size_t(p)], e = ps.patch_ptr[size_t(p) + 1];
+        bad += e - b > ts || e <= b;
+        for (int64_t i = b; i < e; ++i) {
+            const int32_t v = ps.patch_rows[size_t(i)];
+            bad += M.fixed[size_t(v)] != 0 || owner[size_t(v)] >= 0;
+            owner[size_t(v)] = p;
+        }
+    }
+    for (int32_t v = 0; v < M.n; ++v) bad += !M.fixed[size_t(v)] && owner[size_t(v)] < 0;
+    std::vector<uint8_t> seen(size_t(M.n), 0);
+    for (int32_t p = 0; p < np; ++p) {
+        const int64_t b = ps.patch_ptr[size_t(p)], e = ps.patch_ptr[size_t(p) + 1];
+        if (e <= b) continue;
+        std::vector<int32_t> queue(1, ps.patch_rows[size_t(b)]);
+        seen[size_t(queue[0])] = 1;
+        for (size_t h = 0; h < queue.size(); ++h)
+            for (int32_t j = M.row_ptr[queue[h]]; j < M.row_ptr[queue[h] + 1]; ++j) {
+                const int32_t u = M.col[size_t(j)];
+                if (owner[size_t(u)] == p && !seen[size_t(u)]) {
+                    seen[size_t(u)] = 1;
+                    queue.push_back(u);
+                }
+            }
+        bad += int64_t(queue.size()) != e - b;
+    }
+    return bad;
+}
+
 // The planted weight: the first triangle record's weight as if its second
 // corner were in one triangle more.
 template <class Plan, class RowOf>
@@ -390,6 +426,15 @@ int main(int argc, char **argv) {
         }
         const double q_direct = quality_sum_direct(M, x, y);
         auto q_err = [&](double q_plan) { return std::fabs(q_plan - q_direct) / q_direct; };
+
+        // the patches the patch plans grow from: every free row in exactly one
+        // patch, at most ts rows each, each patch connected over the adjacency
+        for (int ts : {256, 1024}) {
+            const Mesh::Patches &ps = lms::patch_set(M, ts);
+            const long bad = check_patches(M, ps, ts);
+            total_bad += bad;
+            std::printf("patches ts=%d count=%d wrong=%ld\n", ts, int(ps.patch_ptr.size()) - 1, bad);
+        }
 
         // single-sweep halo plans: {tile size}
         for (int ts : {128, 256}) {

@@ -59,12 +59,20 @@ def mesh_file(tmp_path_factory):
     return str(path)
 
 
-def run(plan_sim, mesh_file, *args):
+PATCHES = re.compile(r"^patches ts=(\d+) count=(\d+) wrong=(\d+)$")
+
+
+def run(plan_sim, mesh_file, *args, patches=None):
     r = subprocess.run([plan_sim, mesh_file, *args], capture_output=True, text=True, timeout=300)
     lines = r.stdout.splitlines()
     # the arrays the relabelling installed (padded copies, triangles, lists)
     assert lines and lines[0] == "relabel wrong=0", r.stdout + r.stderr
-    rows = [LINE.match(line) for line in lines[1:]]
+    # the patch sets of 256 and 1024 rows
+    prow = [PATCHES.match(line) for line in lines[1:3]]
+    assert all(prow), r.stdout + r.stderr
+    if patches is not None:
+        patches.extend((int(g[1]), int(g[2]), int(g[3])) for g in prow)
+    rows = [LINE.match(line) for line in lines[3:]]
     assert all(rows) and len(rows) == 18, r.stdout + r.stderr
     return r.returncode, [(g[1], g[2], int(g[3]), int(g[4]), g[5] == "1", int(g[7]), g[8] == "1", float(g[9]))
                           for g in rows]
@@ -72,8 +80,11 @@ def run(plan_sim, mesh_file, *args):
 
 @pytest.mark.parametrize("ordering", ["ori", "bfs", "rdr", "random"])
 def test_plans_reproduce_plain_sweeps_bit_for_bit(plan_sim, mesh_file, ordering):
-    rc, rows = run(plan_sim, mesh_file, ordering)
+    patches = []
+    rc, rows = run(plan_sim, mesh_file, ordering, patches=patches)
     assert rc == 0, rows
+    # patches partition the free rows into connected pieces of at most ts rows
+    assert all(wrong == 0 for _, _, wrong in patches), patches
     assert all(r[5] == 0 for r in rows), rows
     fit = [r for r in rows if r[4]]
     # the fused-quality records sum to the definition's n*Q (another order)
@@ -83,6 +94,21 @@ def test_plans_reproduce_plain_sweeps_bit_for_bit(plan_sim, mesh_file, ordering)
     assert len(fit) >= (10 if ordering == "random" else 14), rows
     # several sweeps per pass are covered for both plan kinds
     assert any(r[0] == "tb" and r[3] == 4 for r in fit) and any(r[0] == "mc" and r[3] == 3 for r in fit)
+
+
+def test_patch_growth_leaves_few_fragments_under_every_ordering(plan_sim, mesh_file):
+    # each patch grows from the border of those before it, so the labels
+    # barely change how many patches the free rows fall into
+    counts = {}
+    for ordering in ("ori", "bfs", "rdr", "random"):
+        patches = []
+        run(plan_sim, mesh_file, ordering, patches=patches)
+        counts[ordering] = {ts: count for ts, count, _ in patches}
+    m = meshgen.jittered_grid(211, 173, seed=17, land_fraction=0.3)
+    for ts in (256, 1024):
+        low = min(c[ts] for c in counts.values())
+        assert all(c[ts] <= 1.2 * low for c in counts.values()), counts
+        assert low >= m.n * 0.6 / ts, counts  # at least the free rows / ts
 
 
 def test_planted_mistakes_are_caught(plan_sim, mesh_file):
